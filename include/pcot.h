@@ -1,0 +1,199 @@
+/*
+ * pcot.h - C ABI of the MI355X (gfx950) library that runs polyhedral loop nests
+ * (iterative stencils and interval dynamic programming) under single-level
+ * tiling and under cache-oblivious recursive decomposition.
+ *
+ * Problem statement followed (paper: "PCOT: Cache Oblivious Tiling of
+ * Polyhedral Programs", arXiv 1802.00166):
+ *   - the input is a fully permutable loop nest, described by its domain and
+ *     its dependences (Section 3, Tiling; Section 4.1 Approach Overview);
+ *   - tiles are hyper-rectangles of runtime sizes b_i; the tile size is the
+ *     base-case (leaf) threshold of the recursive decomposition (Section 3.3,
+ *     Terminology: Tile Size);
+ *   - the schedule is either single-level tiling visiting tiles in
+ *     lexicographic or wavefront order, or the cache-oblivious recursion that
+ *     halves the padded bounding box into 2^d orthants (Section 4.2), skips
+ *     zero and empty orthants (Section 4.3) and pads the bounding box to
+ *     b_i * 2^k_i (Section 4.5).
+ * Stencils are skewed (t, i) -> (t, i + t) in every spatial dimension to make
+ * the nest fully permutable (Section 4.3.2, the Heat-2D skewing example;
+ * appendix on memory allocation, the 1D-Jacobi schedule), and values are
+ * stored in two buffers indexed by t mod 2 (the appendix's motivating
+ * example), which is a schedule-independent allocation for these radius-1
+ * stencils.
+ *
+ * Conventions for every entry point
+ *   - Pointers named "device" are HIP device pointers; everything else is
+ *     host memory.  The caller owns every buffer it passes.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Run calls only enqueue work and return; results and device-side errors
+ *     are visible after the stream is synchronised (pcot_stream_status).
+ *   - Returns PCOT_OK (0) or a negative pcot_status; pcot_last_error() then
+ *     gives a message (thread-local, valid until the next call on the thread).
+ *   - No C++ exception crosses this boundary.
+ */
+#ifndef PCOT_H
+#define PCOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ enums --- */
+
+typedef enum {
+    PCOT_JACOBI1D_3PT = 1, /* u'[i] = ((u[i-1] + u[i]) + u[i+1]) / 3                        */
+    PCOT_JACOBI2D_5PT = 2, /* u' = 0.2 * ((((c + n) + s) + e) + w), n = u[y-1][x], e = u[y][x+1] */
+    PCOT_HEAT3D_7PT = 3    /* u' = u + 0.125 * ((dx + dy) + dz), dx = (u[x+1] - 2u) + u[x-1]   */
+} pcot_kind;
+
+typedef enum {
+    PCOT_F64 = 0,  /* storage and arithmetic in binary64                                   */
+    PCOT_F32 = 1,  /* storage and arithmetic in binary32                                   */
+    PCOT_BF16 = 2  /* bfloat16 storage (uint16 bit patterns), binary32 arithmetic, each
+                      stored value rounded to nearest-even bfloat16                        */
+} pcot_dtype;
+
+typedef enum {
+    PCOT_NAIVE = 0,    /* untiled: one sweep over the field per time step                     */
+    PCOT_SLT_LEX = 1,  /* single-level tiling, tiles in lexicographic order (Section 1, 3.2)   */
+    PCOT_SLT_WAVE = 2, /* single-level tiling, tiles ordered by wavefront, then lexicographic  */
+    PCOT_COT_SEQ = 3,  /* recursive decomposition, orthants in lexicographic order (Sec. 4.2)  */
+    PCOT_COT_PAR = 4   /* recursive decomposition, orthants grouped by wavefront at each level
+                          (the task/taskwait grouping of the parallel version, Sec. 4.2)      */
+} pcot_schedule;
+
+typedef int32_t pcot_status;
+#define PCOT_OK 0
+#define PCOT_ERR_INVALID (-1)     /* bad kind, dtype, dims, T, tile or pointer              */
+#define PCOT_ERR_UNSUPPORTED (-2) /* valid tile that the executors cannot run (registers/LDS) */
+#define PCOT_ERR_OVERFLOW (-3)    /* DP: (N-1)*pmax^3 does not fit in int64                  */
+#define PCOT_ERR_HIP (-4)         /* a HIP runtime call failed                              */
+#define PCOT_ERR_WORKSPACE (-5)   /* workspace missing or smaller than required            */
+#define PCOT_ERR_TIMEOUT (-6)     /* device watchdog: a tile waited too long for its inputs */
+#define PCOT_ERR_DEVICE (-7)      /* device-side validation failed (e.g. p out of range)    */
+
+/* Leaf (tile) sizes.  t: time steps per tile; s[0..d-1]: spatial sizes, outer
+ * to inner, in skewed coordinates (j = i + t).  The same numbers are the
+ * base-case thresholds of the recursive schedules.  For the interval DP,
+ * s[0], s[1], s[2] are the (i, j, k) block sizes and t is unused. */
+typedef struct {
+    int32_t t;
+    int32_t s[3];
+} pcot_tile;
+
+/* ------------------------------------------------------------ stencils --- */
+
+/* Bytes of workspace pcot_stencil_run needs for this problem (0 when the
+ * arguments are invalid; see pcot_last_error).  Covers the second
+ * time-level buffer, tile dependency counters and the device error word. */
+size_t pcot_stencil_workspace(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T,
+                              const pcot_tile* tile, int32_t schedule);
+
+/* Run T time steps of stencil `kind` on the field `in`, writing u_T to `out`.
+ *   dims      host, d entries (d = 1, 2, 3 for the three kinds), array extents
+ *             outer to inner INCLUDING the boundary; each >= 3.  Row-major,
+ *             innermost index contiguous, no padding.
+ *   T         >= 0 time steps.  T = 0 copies in to out.
+ *   tile      host; ignored for PCOT_NAIVE (may be NULL then).
+ *   in        device, read only, prod(dims) elements of `dtype`.
+ *   out       device, prod(dims) elements; must not overlap `in` or the
+ *             workspace.  Boundary cells (outer face) are copied from `in`
+ *             unchanged; interior cells receive u_T.
+ *   workspace device, at least pcot_stencil_workspace(...) bytes, 256-byte
+ *             aligned; contents are scratch between calls.  Calls that share
+ *             a workspace must be ordered on one stream.
+ * Every schedule and every valid tile gives the same bits (the method only
+ * reorders points of a fully permutable nest; each point uses the fixed
+ * operation order of its update rule, without contraction to FMA). */
+pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T,
+                             const pcot_tile* tile, int32_t schedule, const void* in, void* out,
+                             void* workspace, size_t ws_bytes, void* stream);
+
+/* Is `tile` runnable by the tiled executors for this kind and dtype?  Returns
+ * PCOT_OK, PCOT_ERR_UNSUPPORTED or PCOT_ERR_INVALID without touching the GPU. */
+pcot_status pcot_stencil_tile_supported(int32_t kind, int32_t dtype, const pcot_tile* tile);
+
+/* Batched form: n independent instances of one kind and dtype, each with its
+ * own dims, T and tile, run by one persistent launch that takes tiles of all
+ * instances from one device queue.
+ *   dims   host, n*3 (unused trailing entries ignored), in/out host arrays of
+ *          n device pointers.  T, tiles host arrays of n.
+ *   workspace >= pcot_stencil_workspace_batched(...).
+ * Schedules: PCOT_SLT_WAVE or PCOT_COT_PAR (order within each instance);
+ * instances are interleaved heaviest first. */
+size_t pcot_stencil_workspace_batched(int32_t kind, int32_t dtype, int32_t n, const int64_t* dims,
+                                      const int64_t* T, const pcot_tile* tiles, int32_t schedule);
+pcot_status pcot_stencil_run_batched(int32_t kind, int32_t dtype, int32_t n, const int64_t* dims,
+                                     const int64_t* T, const pcot_tile* tiles, int32_t schedule,
+                                     const void* const* in, void* const* out, void* workspace,
+                                     size_t ws_bytes, void* stream);
+
+/* Number of leaves (non-empty tiles) the planner emits for this problem, and
+ * optionally their visiting order: `order` (host, may be NULL) receives up to
+ * `cap` entries of 4 int32 each (time tile index, then spatial tile indices
+ * outer to inner, unused entries 0).  Host only; no GPU work. */
+int64_t pcot_stencil_plan(int32_t kind, const int64_t* dims, int64_t T, const pcot_tile* tile,
+                          int32_t schedule, int32_t* order, int64_t cap);
+
+/* Device error-norm reduction in binary64 for reporting precision forms:
+ * over the interior of a field of `dims` (d entries), with x of `dtype` and
+ * the reference r in binary64 (both device), writes (host) out[0] =
+ * max|x-r|, out[1] = max|r|, out[2] = sum (x-r)^2, out[3] = sum r^2.
+ * Synchronises the stream. */
+pcot_status pcot_error_norms(int32_t dtype, int32_t d, const int64_t* dims, const void* x,
+                             const double* r, double* out, void* stream);
+
+/* --------------------------------------------------------- interval DP --- */
+
+/* Matrix-chain / optimal parenthesization (the interval DP of the paper's OSP
+ * benchmark, Section 5.1.2, tiled in all three dimensions after the
+ * Guibas-Kung-Thompson reordering of the reduction):
+ *   C[i][i] = 0,  C[i][j] = min_{i<=k<j} C[i][k] + C[k+1][j] + p[i-1] p[k] p[j].
+ *   p      device, N+1 int64 dimensions, each in [1, pmax].
+ *   pmax   caller's bound on p; selects 32-bit arithmetic when
+ *          (N-1)*pmax^3 < 2^32 (exact then), int64 otherwise;
+ *          PCOT_ERR_OVERFLOW when (N-1)*pmax^3 >= 2^62.  The kernels check
+ *          1 <= p <= pmax and report PCOT_ERR_DEVICE through
+ *          pcot_stream_status if not.
+ *   C      device, N*N int64 row-major; C[(i-1)*N + (j-1)] receives the
+ *          cost of A_i..A_j for i <= j.  The lower triangle is set to 0.
+ *   tile   s[0] = s[1] = block size b of the (i, j) tiles (16..256, power of
+ *          two), s[2] = k-block size (multiple of 16, <= b); t unused.
+ *   schedule PCOT_SLT_WAVE (tile diagonals in order) or PCOT_COT_PAR
+ *          (recursive halving of the padded (i, j) triangle; leaves grouped by
+ *          the wavefronts of each split).
+ * Every schedule and tile gives identical (exact integer) results. */
+size_t pcot_dp_workspace(int64_t N, const pcot_tile* tile, int32_t schedule);
+pcot_status pcot_dp_run(const int64_t* p, int64_t N, int64_t pmax, const pcot_tile* tile,
+                        int32_t schedule, int64_t* C, void* workspace, size_t ws_bytes,
+                        void* stream);
+
+/* ------------------------------------------------------------ status --- */
+
+/* Synchronises `stream` and reads the device error word that the last run on
+ * `workspace` left: PCOT_OK, PCOT_ERR_TIMEOUT or PCOT_ERR_DEVICE. */
+pcot_status pcot_stream_status(void* workspace, void* stream);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* pcot_last_error(void);
+
+/* Measurement: when enabled, every run records a HIP event pair on its
+ * stream around its dominant kernel (the tiled executor, or the DP tile
+ * kernels).  pcot_kernel_timing(1) starts a new measurement (discarding old
+ * events); pcot_kernel_timing_read waits for the recorded events and returns
+ * the summed kernel time (ms) and the number of timed launches. */
+pcot_status pcot_kernel_timing(int32_t enable);
+pcot_status pcot_kernel_timing_read(double* total_ms, int64_t* count);
+
+/* Library version string. */
+const char* pcot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCOT_H */

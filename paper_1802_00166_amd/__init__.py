@@ -1,0 +1,175 @@
+"""Python binding of libpcot.so (the MI355X tiled / cache-oblivious loop-nest library).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/pcot.h.  PyTorch provides device
+memory and streams.  There is no CPU fallback: importing this package raises
+if the library has not been built (python -m paper_1802_00166_amd.build or
+__graft_entry__.build()).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcot.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libpcot.so is not built at %s; run __graft_entry__.build()" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# enums (include/pcot.h)
+JACOBI1D, JACOBI2D, HEAT3D = 1, 2, 3
+F64, F32, BF16 = 0, 1, 2
+NAIVE, SLT_LEX, SLT_WAVE, COT_SEQ, COT_PAR = 0, 1, 2, 3, 4
+KINDS = {"jacobi1d": JACOBI1D, "jacobi2d": JACOBI2D, "heat3d": HEAT3D}
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
+SCHEDULES = {"naive": NAIVE, "slt_lex": SLT_LEX, "slt_wave": SLT_WAVE, "cot_seq": COT_SEQ, "cot_par": COT_PAR}
+STATUS = {0: "OK", -1: "INVALID", -2: "UNSUPPORTED", -3: "OVERFLOW", -4: "HIP", -5: "WORKSPACE",
+          -6: "TIMEOUT", -7: "DEVICE"}
+
+
+class pcot_tile(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int32), ("s", ctypes.c_int32 * 3)]
+
+
+class PcotError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+_I32, _I64, _SZ, _P = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_TP = ctypes.POINTER(pcot_tile)
+
+_SIGS = {
+    "pcot_stencil_workspace": (_SZ, [_I32, _I32, _I64P, _I64, _TP, _I32]),
+    "pcot_stencil_run": (_I32, [_I32, _I32, _I64P, _I64, _TP, _I32, _P, _P, _P, _SZ, _P]),
+    "pcot_stencil_tile_supported": (_I32, [_I32, _I32, _TP]),
+    "pcot_stencil_plan": (_I64, [_I32, _I64P, _I64, _TP, _I32, ctypes.POINTER(ctypes.c_int32), _I64]),
+    "pcot_stream_status": (_I32, [_P, _P]),
+    "pcot_last_error": (ctypes.c_char_p, []),
+    "pcot_version": (ctypes.c_char_p, []),
+    "pcot_kernel_timing": (_I32, [_I32]),
+    "pcot_kernel_timing_read": (_I32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+
+def optional_symbol(name, restype, argtypes):
+    """Binds an entry point declared in include/pcot.h (None if not exported)."""
+    f = getattr(_lib, name, None)
+    if f is not None:
+        f.restype = restype
+        f.argtypes = argtypes
+    return f
+
+
+def last_error() -> str:
+    return (_lib.pcot_last_error() or b"").decode()
+
+
+def check(status: int) -> None:
+    if status != 0:
+        raise PcotError(status, last_error())
+
+
+def make_tile(t: int, *s: int) -> pcot_tile:
+    s = list(s) + [0] * (3 - len(s))
+    return pcot_tile(int(t), (ctypes.c_int32 * 3)(*[int(v) for v in s]))
+
+
+def _dims(shape):
+    return (ctypes.c_int64 * 3)(*(list(int(v) for v in shape) + [0] * (3 - len(shape))))
+
+
+# ------------------------------------------------------------ torch layer ---
+def _torch():
+    import torch
+    return torch
+
+
+def storage_dtype(dtype: str):
+    torch = _torch()
+    return {"f64": torch.float64, "f32": torch.float32, "bf16": torch.int16}[dtype]
+
+
+def stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace_bytes(kind: str, dtype: str, shape, T: int, tile, schedule: str) -> int:
+    tp = tile if isinstance(tile, pcot_tile) else (make_tile(*tile) if tile is not None else None)
+    n = pcot_stencil_workspace(KINDS[kind], DTYPES[dtype], _dims(shape), int(T),
+                               ctypes.byref(tp) if tp is not None else None, SCHEDULES[schedule])
+    if n == 0:
+        raise PcotError(-1, last_error())
+    return int(n)
+
+
+def alloc_workspace(nbytes: int, device="cuda:0"):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def stencil_run(kind: str, dtype: str, x, T: int, tile=None, schedule: str = "naive", out=None,
+                workspace=None, stream=None):
+    """Runs T steps on device tensor x (shape = field extents incl. boundary).
+
+    bf16 fields are int16 tensors holding bfloat16 bit patterns.  Returns out.
+    """
+    torch = _torch()
+    assert x.is_cuda and x.is_contiguous()
+    if out is None:
+        out = torch.empty_like(x)
+    tp = tile if isinstance(tile, pcot_tile) else (make_tile(*tile) if tile is not None else None)
+    nbytes = workspace_bytes(kind, dtype, x.shape, T, tp, schedule)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = alloc_workspace(nbytes, x.device)
+    st = pcot_stencil_run(KINDS[kind], DTYPES[dtype], _dims(x.shape), int(T),
+                          ctypes.byref(tp) if tp is not None else None, SCHEDULES[schedule],
+                          ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                          ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()),
+                          stream_ptr(stream))
+    check(st)
+    return out
+
+
+def stream_status(workspace, stream=None) -> int:
+    return int(pcot_stream_status(ctypes.c_void_p(workspace.data_ptr()), stream_ptr(stream)))
+
+
+def kernel_timing(enable: bool) -> None:
+    check(pcot_kernel_timing(1 if enable else 0))
+
+
+def kernel_timing_read():
+    ms = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    check(pcot_kernel_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def tile_supported(kind: str, dtype: str, tile) -> bool:
+    tp = tile if isinstance(tile, pcot_tile) else make_tile(*tile)
+    return pcot_stencil_tile_supported(KINDS[kind], DTYPES[dtype], ctypes.byref(tp)) == 0
+
+
+def plan(kind: str, shape, T: int, tile, schedule: str):
+    """Leaf visiting order the planner emits (host only): list of tuples."""
+    tp = tile if isinstance(tile, pcot_tile) else make_tile(*tile)
+    d = len(shape)
+    n = pcot_stencil_plan(KINDS[kind], _dims(shape), int(T), ctypes.byref(tp), SCHEDULES[schedule], None, 0)
+    if n < 0:
+        raise PcotError(-1, last_error())
+    buf = (ctypes.c_int32 * (4 * max(n, 1)))()
+    pcot_stencil_plan(KINDS[kind], _dims(shape), int(T), ctypes.byref(tp), SCHEDULES[schedule], buf, n)
+    return [tuple(buf[4 * i: 4 * i + d + 1]) for i in range(n)]

@@ -1,0 +1,394 @@
+// C ABI: argument validation, plan cache, workspace layout and launches.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pcot.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace pcot {
+bool tiled2d_supported(const int* b);
+hipError_t launch_tiled2d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
+bool tiled1d_supported(const int* b);
+hipError_t launch_tiled1d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
+bool tiled3d_supported(const int* b);
+hipError_t launch_tiled3d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
+}  // namespace pcot
+
+using namespace pcot;
+
+namespace {
+
+thread_local std::string g_err;
+
+pcot_status fail(pcot_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(PCOT_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t elem_bytes(int dtype) { return dtype == PCOT_F64 ? 8 : dtype == PCOT_F32 ? 4 : 2; }
+
+int kind_dims(int kind) { return kind == PCOT_JACOBI1D_3PT ? 1 : kind == PCOT_JACOBI2D_5PT ? 2 : kind == PCOT_HEAT3D_7PT ? 3 : 0; }
+
+long long watchdog_ticks() {
+    // wall_clock64 runs at hipDeviceAttributeWallClockRate kHz; allow 4 s.
+    static long long ticks = 0;
+    if (!ticks) {
+        int dev = 0, khz = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            khz = 100000;
+        ticks = (long long)khz * 1000LL * 4LL;
+    }
+    return ticks;
+}
+
+// ------------------------------------------------------------- validation ---
+struct Prob {
+    int kind = 0, dtype = 0, d = 0, sched = 0;
+    int64_t n[3] = {1, 1, 1};
+    int64_t T = 0;
+    int b[4] = {1, 1, 1, 1};   // t, spatial outer..inner
+    int64_t elems = 0;
+};
+
+pcot_status validate(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T, const pcot_tile* tile,
+                     int32_t schedule, Prob& p) {
+    p.kind = kind;
+    p.dtype = dtype;
+    p.d = kind_dims(kind);
+    p.sched = schedule;
+    if (!p.d) return fail(PCOT_ERR_INVALID, "unknown kind %d", kind);
+    if (dtype < PCOT_F64 || dtype > PCOT_BF16) return fail(PCOT_ERR_INVALID, "unknown dtype %d", dtype);
+    if (schedule < PCOT_NAIVE || schedule > PCOT_COT_PAR) return fail(PCOT_ERR_INVALID, "unknown schedule %d", schedule);
+    if (!dims) return fail(PCOT_ERR_INVALID, "dims is NULL");
+    if (T < 0 || T > (1 << 30)) return fail(PCOT_ERR_INVALID, "T=%lld out of range", (long long)T);
+    p.T = T;
+    p.elems = 1;
+    for (int i = 0; i < p.d; ++i) {
+        if (dims[i] < 3 || dims[i] > (1LL << 30)) return fail(PCOT_ERR_INVALID, "dims[%d]=%lld (need 3 .. 2^30)", i, (long long)dims[i]);
+        p.n[i] = dims[i];
+        p.elems *= dims[i];
+    }
+    if (p.elems > (1LL << 36)) return fail(PCOT_ERR_INVALID, "field too large");
+    if (schedule != PCOT_NAIVE) {
+        if (!tile) return fail(PCOT_ERR_INVALID, "tile is NULL for a tiled schedule");
+        if (tile->t < 1) return fail(PCOT_ERR_INVALID, "tile.t=%d < 1", tile->t);
+        p.b[0] = tile->t;
+        for (int i = 0; i < p.d; ++i) {
+            if (tile->s[i] < 2) return fail(PCOT_ERR_INVALID, "tile.s[%d]=%d < 2 (dependence distance is 2)", i, tile->s[i]);
+            p.b[i + 1] = tile->s[i];
+        }
+        if (p.elems > (1LL << 31) - 1) return fail(PCOT_ERR_UNSUPPORTED, "tiled executors index fields below 2^31 elements");
+    }
+    return PCOT_OK;
+}
+
+bool tile_ok(int kind, const int* b) {
+    int bb[4] = {b[0], b[1], b[2], b[3]};
+    switch (kind) {
+        case PCOT_JACOBI1D_3PT: return tiled1d_supported(bb);
+        case PCOT_JACOBI2D_5PT: return tiled2d_supported(bb);
+        default: return tiled3d_supported(bb);
+    }
+}
+
+// ---------------------------------------------------------------- plans ---
+struct DevPlan {
+    std::vector<QEntry> host;
+    QEntry* dev = nullptr;
+    int device = -1;
+    int64_t cnt[4] = {1, 1, 1, 1};
+    ~DevPlan() {
+        if (dev) (void)hipFree(dev);
+    }
+};
+
+std::mutex g_mu;
+std::map<std::vector<int64_t>, std::unique_ptr<DevPlan>> g_plans;
+
+StencilGeom geom_of(const Prob& p) {
+    int64_t tb[4] = {p.b[0], p.b[1], p.b[2], p.b[3]};
+    return make_geom(p.d, p.n, p.T, tb);
+}
+
+pcot_status get_plan(const Prob& p, DevPlan** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::vector<int64_t> key = {dev, p.d, p.n[0], p.n[1], p.n[2], p.T, p.b[0], p.b[1], p.b[2], p.b[3], p.sched};
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        *out = it->second.get();
+        return PCOT_OK;
+    }
+    StencilGeom g = geom_of(p);
+    for (int i = 0; i <= p.d; ++i)
+        if (g.cnt[i] >= 65535) return fail(PCOT_ERR_UNSUPPORTED, "tile grid too large along dim %d", i);
+    std::vector<Leaf> leaves = enumerate_leaves(g, p.sched);
+    auto P = std::make_unique<DevPlan>();
+    P->device = dev;
+    for (int i = 0; i < 4; ++i) P->cnt[i] = g.cnt[i];
+    P->host.resize(leaves.size());
+    for (size_t i = 0; i < leaves.size(); ++i)
+        for (int j = 0; j < 4; ++j) P->host[i].k[j] = (uint16_t)leaves[i].k[j];
+    if (!leaves.empty()) {
+        HIP_TRY(hipMalloc(&P->dev, sizeof(QEntry) * leaves.size()));
+        HIP_TRY(hipMemcpy(P->dev, P->host.data(), sizeof(QEntry) * leaves.size(), hipMemcpyHostToDevice));
+    }
+    *out = P.get();
+    g_plans.emplace(key, std::move(P));
+    return PCOT_OK;
+}
+
+// ------------------------------------------------------------ workspace ---
+struct WsLayout {
+    size_t hdr = 0, probs = 0, counters = 0, field = 0, total = 0;
+    size_t ncounters = 0;
+};
+
+WsLayout ws_layout(const Prob& p) {
+    WsLayout L;
+    L.hdr = 0;
+    size_t off = align_up(HDR_WORDS * sizeof(unsigned));
+    L.probs = off;
+    off += align_up(sizeof(TiledProblem));
+    if (p.sched != PCOT_NAIVE) {
+        StencilGeom g = geom_of(p);
+        size_t nc = 1;
+        for (int i = 0; i <= p.d; ++i) nc *= (size_t)g.cnt[i];
+        L.ncounters = nc;
+        L.counters = off;
+        off += align_up(nc * sizeof(unsigned));
+    }
+    L.field = off;
+    off += align_up((size_t)p.elems * elem_bytes(p.dtype));
+    L.total = off;
+    return L;
+}
+
+TiledProblem make_tiled(const Prob& p, const DevPlan* plan, const void* in, void* out, void* ws_field,
+                        unsigned* counters) {
+    TiledProblem P;
+    memset(&P, 0, sizeof P);
+    P.in = in;
+    // u_T lands in buf[T mod 2] = out
+    if (p.T & 1) { P.buf1 = out; P.buf0 = ws_field; }
+    else { P.buf0 = out; P.buf1 = ws_field; }
+    for (int i = 0; i < 3; ++i) P.n[i] = (int)p.n[i];
+    P.T = (int)p.T;
+    for (int i = 0; i < 4; ++i) {
+        P.b[i] = p.b[i];
+        P.cnt[i] = (int)plan->cnt[i];
+    }
+    P.counters = counters;
+    return P;
+}
+
+hipError_t launch_tiled_kind(int kind, int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s) {
+    switch (kind) {
+        case PCOT_JACOBI1D_3PT: return launch_tiled1d(dtype, b, L, grid_cap, s);
+        case PCOT_JACOBI2D_5PT: return launch_tiled2d(dtype, b, L, grid_cap, s);
+        default: return launch_tiled3d(dtype, b, L, grid_cap, s);
+    }
+}
+
+
+// Optional timing of the dominant kernel of each run: an event pair recorded
+// on the launch stream around the executor launch.
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
+
+pcot_status timed_launch_begin(hipStream_t s, hipEvent_t* stop) {
+    *stop = nullptr;
+    if (!g_timing) return PCOT_OK;
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    HIP_TRY(hipEventRecord(a, s));
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_events.emplace_back(a, b);
+    *stop = b;
+    return PCOT_OK;
+}
+
+pcot_status timed_launch_end(hipStream_t s, hipEvent_t stop) {
+    if (stop) HIP_TRY(hipEventRecord(stop, s));
+    return PCOT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pcot_last_error(void) { return g_err.c_str(); }
+const char* pcot_version(void) { return "pcot-mi355x 0.1 (gfx950)"; }
+
+size_t pcot_stencil_workspace(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T, const pcot_tile* tile,
+                              int32_t schedule) {
+    Prob p;
+    if (validate(kind, dtype, dims, T, tile, schedule, p) != PCOT_OK) return 0;
+    return ws_layout(p).total;
+}
+
+pcot_status pcot_stencil_tile_supported(int32_t kind, int32_t dtype, const pcot_tile* tile) {
+    const int d = kind_dims(kind);
+    if (!d) return fail(PCOT_ERR_INVALID, "unknown kind %d", kind);
+    if (dtype < PCOT_F64 || dtype > PCOT_BF16) return fail(PCOT_ERR_INVALID, "unknown dtype %d", dtype);
+    if (!tile || tile->t < 1) return fail(PCOT_ERR_INVALID, "bad tile");
+    int b[4] = {tile->t, 1, 1, 1};
+    for (int i = 0; i < d; ++i) {
+        if (tile->s[i] < 2) return fail(PCOT_ERR_INVALID, "tile.s[%d] < 2", i);
+        b[i + 1] = tile->s[i];
+    }
+    if (!tile_ok(kind, b)) return fail(PCOT_ERR_UNSUPPORTED, "tile (%d; %d,%d,%d) not runnable for kind %d", b[0], b[1], b[2], b[3], kind);
+    return PCOT_OK;
+}
+
+int64_t pcot_stencil_plan(int32_t kind, const int64_t* dims, int64_t T, const pcot_tile* tile, int32_t schedule,
+                          int32_t* order, int64_t cap) {
+    Prob p;
+    if (schedule == PCOT_NAIVE) { fail(PCOT_ERR_INVALID, "naive schedule has no plan"); return -1; }
+    if (validate(kind, PCOT_F64, dims, T, tile, schedule, p) != PCOT_OK) return -1;
+    StencilGeom g = geom_of(p);
+    std::vector<Leaf> leaves = enumerate_leaves(g, schedule);
+    if (order)
+        for (int64_t i = 0; i < (int64_t)leaves.size() && i < cap; ++i)
+            for (int j = 0; j < 4; ++j) order[4 * i + j] = leaves[i].k[j];
+    return (int64_t)leaves.size();
+}
+
+pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T, const pcot_tile* tile,
+                             int32_t schedule, const void* in, void* out, void* workspace, size_t ws_bytes,
+                             void* stream) {
+    Prob p;
+    pcot_status st = validate(kind, dtype, dims, T, tile, schedule, p);
+    if (st != PCOT_OK) return st;
+    if (!in || !out) return fail(PCOT_ERR_INVALID, "in/out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)p.elems * elem_bytes(dtype);
+    {
+        const char* a = (const char*)in;
+        const char* b = (const char*)out;
+        if (a < b + bytes && b < a + bytes) return fail(PCOT_ERR_INVALID, "in and out overlap");
+    }
+    if (schedule != PCOT_NAIVE && !tile_ok(kind, p.b))
+        return fail(PCOT_ERR_UNSUPPORTED, "tile (%d; %d,%d,%d) not runnable for kind %d dtype %d", p.b[0], p.b[1],
+                    p.b[2], p.b[3], kind, dtype);
+    if (T == 0) {
+        HIP_TRY(hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s));
+        return PCOT_OK;
+    }
+    const WsLayout W = ws_layout(p);
+    if (!workspace || ws_bytes < W.total)
+        return fail(PCOT_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, W.total);
+    if (((uintptr_t)workspace) % ALIGN) return fail(PCOT_ERR_INVALID, "workspace not 256-byte aligned");
+    char* ws = (char*)workspace;
+    unsigned* hdr = (unsigned*)(ws + W.hdr);
+    void* field = ws + W.field;
+    {
+        const char* a = (const char*)workspace;
+        const char* b = (const char*)out;
+        if (a < b + bytes && b < a + W.total) return fail(PCOT_ERR_INVALID, "out overlaps the workspace");
+        const char* c = (const char*)in;
+        if (a < c + bytes && c < a + W.total) return fail(PCOT_ERR_INVALID, "in overlaps the workspace");
+    }
+    // buffers: buf[T mod 2] = out, the other one in the workspace; both get in's boundary
+    HIP_TRY(launch_copy_boundary(dtype, in, out, field, p.d, p.n, s));
+    if (schedule == PCOT_NAIVE) {
+        HIP_TRY(launch_fill_u32(hdr, HDR_WORDS, 0u, s));
+        void* buf[2];
+        buf[T & 1] = out;
+        buf[(T + 1) & 1] = field;
+        for (int64_t t = 0; t < T; ++t) {
+            const void* src = t == 0 ? in : buf[t & 1];
+            HIP_TRY(launch_step(kind, dtype, src, buf[(t + 1) & 1], p.n, s));
+        }
+        return PCOT_OK;
+    }
+    DevPlan* plan = nullptr;
+    st = get_plan(p, &plan);
+    if (st != PCOT_OK) return st;
+    unsigned* counters = (unsigned*)(ws + W.counters);
+    HIP_TRY(launch_fill_u32(hdr, HDR_WORDS, 0u, s));
+    HIP_TRY(launch_fill_u32(counters, W.ncounters, 0u, s));
+    if (plan->host.empty()) return PCOT_OK;
+    TiledProblem* probs = (TiledProblem*)(ws + W.probs);
+    HIP_TRY(launch_put_problem(probs, make_tiled(p, plan, in, out, field, counters), s));
+    TiledLaunch L;
+    memset(&L, 0, sizeof L);
+    L.probs = probs;
+    L.queue = plan->dev;
+    L.qprob = nullptr;
+    L.nq = (int)plan->host.size();
+    L.hdr = hdr;
+    L.limit_ticks = watchdog_ticks();
+    hipEvent_t stop;
+    st = timed_launch_begin(s, &stop);
+    if (st != PCOT_OK) return st;
+    HIP_TRY(launch_tiled_kind(kind, dtype, p.b, L, 0, s));
+    return timed_launch_end(s, stop);
+}
+
+pcot_status pcot_stream_status(void* workspace, void* stream) {
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    if (!workspace) return fail(PCOT_ERR_INVALID, "workspace is NULL");
+    unsigned w = 0;
+    HIP_TRY(hipMemcpy(&w, (unsigned*)workspace + HDR_ERROR, sizeof w, hipMemcpyDeviceToHost));
+    if (w == DEVERR_TIMEOUT) return fail(PCOT_ERR_TIMEOUT, "device watchdog: a tile waited more than 4 s for its inputs");
+    if (w == DEVERR_INPUT) return fail(PCOT_ERR_DEVICE, "device validation failed (input out of the stated range)");
+    if (w != 0) return fail(PCOT_ERR_DEVICE, "device error word %u", w);
+    return PCOT_OK;
+}
+
+pcot_status pcot_kernel_timing(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto& e : g_events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    g_events.clear();
+    g_timing = enable != 0;
+    return PCOT_OK;
+}
+
+pcot_status pcot_kernel_timing_read(double* total_ms, int64_t* count) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    double tot = 0.0;
+    for (auto& e : g_events) {
+        HIP_TRY(hipEventSynchronize(e.second));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (count) *count = (int64_t)g_events.size();
+    return PCOT_OK;
+}
+
+
+}  // extern "C"

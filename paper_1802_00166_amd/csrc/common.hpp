@@ -1,0 +1,118 @@
+// Shared device helpers: storage types, exact bf16 conversion, wave shifts,
+// the persistent-queue protocol and the device header layout.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace pcot {
+
+// ------------------------------------------------------------ storage ---
+// S = storage type, A = arithmetic type.  bf16 is stored as its 16-bit
+// pattern; loads widen exactly, stores round to nearest even.
+template <typename S> struct Tr;
+template <> struct Tr<double> {
+    using A = double;
+    static __device__ __forceinline__ A ld(const double* p) { return *p; }
+    static __device__ __forceinline__ void st(double* p, A v) { *p = v; }
+    static __device__ __forceinline__ A rnd(A v) { return v; }
+};
+template <> struct Tr<float> {
+    using A = float;
+    static __device__ __forceinline__ A ld(const float* p) { return *p; }
+    static __device__ __forceinline__ void st(float* p, A v) { *p = v; }
+    static __device__ __forceinline__ A rnd(A v) { return v; }
+};
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    const uint32_t b = __float_as_uint(f);
+    if ((b & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((b >> 16) | 0x40u);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+template <> struct Tr<uint16_t> {
+    using A = float;
+    static __device__ __forceinline__ A ld(const uint16_t* p) { return bf16_to_f32(*p); }
+    static __device__ __forceinline__ void st(uint16_t* p, A v) { *p = f32_to_bf16(v); }
+    static __device__ __forceinline__ A rnd(A v) { return bf16_to_f32(f32_to_bf16(v)); }
+};
+
+// ------------------------------------------------------ update rules ---
+// Operation order is part of the contract (no FMA: built with
+// -ffp-contract=off).
+__device__ __forceinline__ double jac1(double l, double c, double r) { return ((l + c) + r) / 3.0; }
+__device__ __forceinline__ float jac1(float l, float c, float r) { return ((l + c) + r) / 3.0f; }
+__device__ __forceinline__ double jac2(double c, double n, double s, double e, double w) {
+    return 0.2 * ((((c + n) + s) + e) + w);
+}
+__device__ __forceinline__ float jac2(float c, float n, float s, float e, float w) {
+    return 0.2f * ((((c + n) + s) + e) + w);
+}
+__device__ __forceinline__ double heat3(double u, double xp, double xm, double yp, double ym,
+                                        double zp, double zm) {
+    const double dx = (xp - 2.0 * u) + xm;
+    const double dy = (yp - 2.0 * u) + ym;
+    const double dz = (zp - 2.0 * u) + zm;
+    return u + 0.125 * ((dx + dy) + dz);
+}
+__device__ __forceinline__ float heat3(float u, float xp, float xm, float yp, float ym, float zp,
+                                       float zm) {
+    const float dx = (xp - 2.0f * u) + xm;
+    const float dy = (yp - 2.0f * u) + ym;
+    const float dz = (zp - 2.0f * u) + zm;
+    return u + 0.125f * ((dx + dy) + dz);
+}
+
+// ------------------------------------------------------- wave shifts ---
+// Value of lane-1 (DPP wave_shr:1); lane 0 receives `fill`.
+__device__ __forceinline__ float shr1(float v, float fill) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v),
+                                                      0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double shr1(double v, double fill) {
+    const long long vi = __double_as_longlong(v), fi = __double_as_longlong(fill);
+    const int lo = __builtin_amdgcn_update_dpp((int)fi, (int)vi, 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(fi >> 32), (int)(vi >> 32), 0x138, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// -------------------------------------------- persistent queue protocol ---
+__device__ __forceinline__ unsigned ld_relaxed(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave-uniform value (an SGPR): branches on it are scalar, so the compiler
+// cannot turn block-level control flow into divergent per-lane loops.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned uni(unsigned v) { return (unsigned)__builtin_amdgcn_readfirstlane((int)v); }
+
+// Spin until *cnt >= need.  Executed by all 64 lanes of one wave with a
+// wave-uniform loop condition.  Bounded by a wall-clock limit; on expiry sets
+// the error word and the abort flag so that every block drains.  Returns
+// false when the tile must be skipped.
+__device__ __forceinline__ bool wait_ready(const unsigned* cnt, unsigned need, unsigned* hdr,
+                                           long long limit_ticks) {
+    if (need > 0 && uni(ld_relaxed(cnt)) < need) {
+        const long long t0 = wall_clock64();
+        while (uni(ld_relaxed(cnt)) < need) {
+            if (uni(ld_relaxed(hdr + HDR_ABORT))) return false;
+            if (wall_clock64() - t0 > limit_ticks) {
+                if ((threadIdx.x & 63) == 0) {
+                    __hip_atomic_store(hdr + HDR_ERROR, DEVERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(hdr + HDR_ABORT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    return uni(ld_relaxed(hdr + HDR_ABORT)) == 0u;
+}
+
+__device__ __forceinline__ void signal(unsigned* cnt) {
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace pcot
