@@ -1,8 +1,9 @@
 // Time-skewed tile executor for the 5-point Jacobi-2D stencil.  Blocks take
-// tiles from a device queue in schedule order and wait on per-tile
-// dependency counters.
+// tiles from a device queue in schedule order and wait on per-tile dependency
+// counters.
 //
-// A leaf (paper: the base function, Section 4.2) is the box
+// A leaf (the base function of the recursive decomposition, Section 4.2, and
+// equally one single-level tile, Section 3) is the box
 //   t in [t0, t0+nt) x jy in [jy0, jy0+by) x jx in [jx0, jx0+bx)
 // of the skewed space jy = y + t, jx = x + t.  Level t at (jy, jx) updates
 // u_{t+1}[jy-t][jx-t] from level t-1 outputs at
@@ -10,61 +11,36 @@
 // so inside a tile every input comes from the same or a lower row and column.
 //
 // Mapping onto CDNA:
-//  * lanes own columns: lane l holds jx = jx0 + l*C .. + C-1 (bx = 64*C);
-//    the one- and two-column shifts cross lanes with DPP wave_shr:1;
-//  * the block streams along jy; wave g of G owns levels [g*L, g*L+L) and
-//    runs one row behind wave g-1, taking its input row from an LDS handoff
-//    (one barrier per row), so a tile holds bt = G*L levels in registers and
-//    each point crosses HBM once per tile instead of once per step;
+//  * lanes own columns: lane l holds jx = jx0 + l*C .. + C-1 (bx = 64*C); the
+//    one- and two-column shifts cross lanes with DPP wave_shr:1;
+//  * the block streams along jy; compute wave g of G owns levels
+//    [g*L, g*L+L) and runs one row behind wave g-1, taking its input row from
+//    an LDS handoff (one barrier per row); a tile keeps bt = G*L levels in
+//    registers, so each point crosses HBM once per tile, not once per step;
 //  * per level, the two previous input rows live in registers;
-//  * inputs written by other tiles (the bottom plane u_t0, and the two-wide
-//    low faces of every level) are read from the two t-mod-2 field buffers,
-//    where the producing tiles left them; a tile writes its top plane and its
-//    two-wide high faces at every level.
+//  * the bottom plane u_t0 is staged through LDS in chunks of rows loaded by
+//    the whole block one chunk ahead; the two-wide left faces of every level
+//    (written by the left neighbour tile) are fetched one chunk of rows ahead;
+//    the two-wide right faces are staged in LDS and written once per chunk;
+//  * all global memory goes through buffer resources: 32-bit offsets, and
+//    out-of-range offsets read 0 / drop the store, which clips tiles at the
+//    array edge and masks stores without branches.
 // Points outside the interior are carried through unchanged (identity), which
-// reproduces the fixed boundary; outside-array positions never feed an
-// interior point.  Tiles that lie entirely inside the interior take a path
-// without any masking or clamping.
+// reproduces the fixed boundary; positions outside the array never feed an
+// interior point.  Tiles entirely inside the interior take a path with no
+// masks at all.
+#include "bufio.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
+
+#include <type_traits>
+#include <utility>
 
 namespace pcot {
 
 namespace {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-// Buffer selection by bit masks: a conditional pick between two struct
-// fields would be lowered to an indexed load from a stack copy.
-__device__ __forceinline__ uintptr_t pick(uintptr_t a, uintptr_t b, int sel_b) {
-    const uintptr_t m = (uintptr_t)0 - (uintptr_t)(sel_b & 1);
-    return (a & ~m) | (b & m);
-}
-template <typename S>
-__device__ __forceinline__ const S* level_src(const TiledProblem& P, int t) {
-    // buffer holding u_t
-    const uintptr_t b = pick((uintptr_t)P.buf0, (uintptr_t)P.buf1, t);
-    return (const S*)pick(b, (uintptr_t)P.in, t == 0);
-}
-template <typename S>
-__device__ __forceinline__ S* level_dst(const TiledProblem& P, int t) {
-    // buffer receiving u_{t+1} (the output of level t)
-    return (S*)pick((uintptr_t)P.buf0, (uintptr_t)P.buf1, t + 1);
-}
-
-// v[0..N) = u[y][x .. x+N) with clamping to the array when BND.
-template <typename S, bool BND, int N>
-__device__ __forceinline__ void ldseg(const S* base, int ny, int nx, int y, int x,
-                                      typename Tr<S>::A* v) {
-    if (BND) y = clampi(y, 0, ny - 1);
-    const S* row = base + (size_t)y * nx;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        int xx = x + i;
-        if (BND) xx = clampi(xx, 0, nx - 1);
-        v[i] = Tr<S>::ld(row + xx);
-    }
-}
 
 __device__ __forceinline__ bool leaf_nonempty(const TiledProblem& P, int kt, int ky, int kx) {
     if (kt < 0 || ky < 0 || kx < 0 || kt >= P.cnt[0] || ky >= P.cnt[1] || kx >= P.cnt[2]) return false;
@@ -85,90 +61,159 @@ __device__ __forceinline__ bool leaf_interior(const TiledProblem& P, int kt, int
            (jx0 + P.b[2] - 1 - t0 <= P.n[1] - 2);
 }
 
+template <int C, int G> struct Cfg {
+    static constexpr int ROW = 64 * C + 2;          // staged row: 2 left-face values + 64*C columns
+    static constexpr int KB = G == 1 ? 4 : 8;       // bottom-plane rows per staging chunk
+    static constexpr int NPT = (KB * ROW + 64 * G - 1) / (64 * G);
+};
+
+template <typename A, int C, int G> struct Smem {
+    A hand[G][2][Cfg<C, G>::ROW];      // [g]: input row of wave g (g > 0); parity by step
+    A bchunk[2][Cfg<C, G>::KB][Cfg<C, G>::ROW];
+    A lfs[G][128];                     // left faces of the current chunk, per wave
+    A rfs[G][128];                     // right faces of the current chunk, per wave
+    A junk[G][128];                    // sink for the lanes that stage nothing
+    int tk, go;
+};
+
+__device__ __forceinline__ uintptr_t pick(uintptr_t a, uintptr_t b, int sel_b) {
+    const uintptr_t m = (uintptr_t)0 - (uintptr_t)(sel_b & 1);
+    return (a & ~m) | (b & m);
+}
+
+__device__ __forceinline__ const void* uptr(const void* p) {
+    // a wave-uniform pointer moved into SGPRs; the value must already be the
+    // same in every lane (readfirstlane takes the first active lane's value)
+    const uintptr_t v = (uintptr_t)p;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return (const void*)(((uintptr_t)hi << 32) | lo);
+}
+
 template <typename S, int C, int L, int G, bool BND>
 __device__ __forceinline__ void exec_tile(const TiledProblem& P, int kt, int ky, int kx,
-                                          typename Tr<S>::A* hand, typename Tr<S>::A* lfs,
-                                          typename Tr<S>::A* rfs) {
+                                          Smem<typename Tr<S>::A, C, G>& sm) {
     using A = typename Tr<S>::A;
-    constexpr int K = 64 / L;        // rows per staging chunk
-    constexpr int ROW = 64 * C + 2;  // handoff row: 2 left-face values + 64*C columns
+    using CF = Cfg<C, G>;
+    constexpr int ES = sizeof(S);
+    constexpr int ROW = CF::ROW, KB = CF::KB, NPT = CF::NPT;
+    constexpr int K = 64 / L;  // rows per left/right-face chunk
     const int lane = threadIdx.x & 63;
     const int w = uni((int)(threadIdx.x >> 6));
-    const int ny = P.n[0], nx = P.n[1];
-    const int bt = P.b[0], by = P.b[1], bx = 64 * C;
+    const int ny = P.n[0], nx = P.n[1], by = P.b[1], bt = P.b[0];
     const int t0 = kt * bt;
     const int nt = min(bt, P.T - t0);
     const int ttop = t0 + nt - 1;
-    const int jy0 = 1 + ky * by, jx0 = 1 + kx * bx;
+    const int jy0 = 1 + ky * by, jx0 = 1 + kx * (64 * C);
     const int tl0 = t0 + w * L;
     const int nl = clampi(nt - w * L, 0, L);
     const int jxl = jx0 + lane * C;
-    A* mylfs = lfs + w * 128;
-    A* myrfs = rfs + w * 128;
+    const uint32_t bytes = (uint32_t)ny * (uint32_t)nx * ES;
+    const uintptr_t pin = (uintptr_t)uptr(P.in), pb0 = (uintptr_t)uptr(P.buf0), pb1 = (uintptr_t)uptr(P.buf1);
+    // descriptors are built from a uniform pointer picked first: selecting
+    // between two descriptors would be done in VGPRs
+    auto src_of = [&](int t) {  // holds u_t
+        const uintptr_t b = pick(pb0, pb1, t);
+        return make_rsrc(uptr((const void*)pick(b, pin, t == 0)), bytes);
+    };
+    auto dst_of = [&](int t) {  // receives u_{t+1}
+        return make_rsrc(uptr((const void*)pick(pb0, pb1, t + 1)), bytes);
+    };
+    auto row_ok = [&](int y) { return !BND || (y >= 1 && y <= ny - 2); };
+    auto col_ok = [&](int x) { return !BND || (x >= 1 && x <= nx - 2); };
+    auto ld = [&](rsrc_t r, int y, int x) -> A {
+        // outside the array: offset out of range (reads 0) or another row (never used)
+        if (BND && (y < 0 || y >= ny)) return A(0);
+        return IO<S>::ld(r, (y * nx + x) * ES);
+    };
+    auto st = [&](rsrc_t r, int y, int x, bool ok, A v) { IO<S>::st(r, ok ? (y * nx + x) * ES : OOB, v); };
 
+    // per level: the two previous input rows (jy-1, jy-2) and lane-1's last
+    // values of them
     A in1[L][C], in2[L][C], x1a[L], x1b[L], x2a[L];
-    // ---- bottom faces: level t's input rows jy0-1 and jy0-2
+    unsigned colok = 0xFFFFFFFFu;  // BND: bit l*C+c = column c of level l is interior
+    if (BND) {
+        colok = 0;
 #pragma unroll
-    for (int l = 0; l < L; ++l) {
-        if (l < nl) {
-            const int t = tl0 + l;
-            const S* src = level_src<S>(P, t);
-            A seg[C + 2];
-            ldseg<S, BND, C + 2>(src, ny, nx, jy0 - t, jxl - t - 1, seg);
-            x1b[l] = seg[0];
-            x1a[l] = seg[1];
+        for (int l = 0; l < L; ++l)
 #pragma unroll
-            for (int c = 0; c < C; ++c) in1[l][c] = seg[2 + c];
-            A seg2[C + 1];
-            ldseg<S, BND, C + 1>(src, ny, nx, jy0 - t - 1, jxl - t, seg2);
-            x2a[l] = seg2[0];
-#pragma unroll
-            for (int c = 0; c < C; ++c) in2[l][c] = seg2[1 + c];
-        }
+            for (int c = 0; c < C; ++c) {
+                const int x = jxl + c - (tl0 + l);
+                colok |= (x >= 1 && x <= nx - 2) ? (1u << (l * C + c)) : 0u;
+            }
     }
-
-    // ---- left faces (level t output at jx0-2, jx0-1), prefetched one chunk ahead:
-    // lane i of the wave carries (row r0 + i / L, level i % L).
-    A lfp0 = A(0), lfp1 = A(0);
+    A lfp0 = A(0), lfp1 = A(0);  // left-face prefetch: lane -> (row, level)
+    // lane i carries (row, level i % L): the level, hence the buffer parity,
+    // differs between lanes, so both uniform descriptors are read (one offset
+    // out of range) and the right value is selected
+    const rsrc_t rdE = dst_of(tl0), rdO = dst_of(tl0 + 1);  // levels tl0 + even / odd l
+    const bool lf_even = ((lane % L) & 1) == 0;
     auto lf_fetch = [&](int r0) {
         const int rr = r0 + lane / L, l = lane % L, t = tl0 + l;
         if (rr < by && l < nl && t < ttop) {
-            const S* src = (const S*)level_dst<S>(P, t);
-            A v[2];
-            ldseg<S, BND, 2>(src, ny, nx, jy0 + rr - t, jx0 - t - 2, v);
-            lfp0 = v[0];
-            lfp1 = v[1];
+            const int y = jy0 + rr - t, x = jx0 - t - 2;
+            const int o = (BND && (y < 0 || y >= ny)) ? OOB : (y * nx + x) * ES;
+            const A aE = IO<S>::ld(rdE, lf_even ? o : OOB), aO = IO<S>::ld(rdO, lf_even ? OOB : o);
+            const A bE = IO<S>::ld(rdE, lf_even ? o + ES : OOB), bO = IO<S>::ld(rdO, lf_even ? OOB : o + ES);
+            lfp0 = lf_even ? aE : aO;
+            lfp1 = lf_even ? bE : bO;
         }
     };
-    // bottom plane (wave 0, level t0 input), prefetched one row ahead
-    A bpn[C + 2];
-    const S* bsrc = level_src<S>(P, t0);
-    if (w == 0) ldseg<S, BND, C + 2>(bsrc, ny, nx, jy0 - t0 + 1, jxl - t0 - 1, bpn);
-    if (nl > 0) lf_fetch(0);
+    A bst[NPT];  // bottom-plane prefetch
+    const rsrc_t rbot = src_of(t0);
+    auto chunk_fetch = [&](int c) {
+        const int bx0 = jx0 - t0 - 1;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int idx = threadIdx.x + i * 64 * G;
+            const int rr = c * KB + idx / ROW;
+            if ((KB * ROW) % (64 * G) == 0 || idx < KB * ROW)
+                bst[i] = rr < by ? ld(rbot, jy0 + rr - t0 + 1, bx0 + idx % ROW) : A(0);
+        }
+    };
+    auto chunk_store = [&](int c) {
+        A* dstc = &sm.bchunk[c & 1][0][0];
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int idx = threadIdx.x + i * 64 * G;
+            if ((KB * ROW) % (64 * G) == 0 || idx < KB * ROW) dstc[idx] = bst[i];
+        }
+    };
 
-    const int nsteps = by + G - 1;
-    for (int S_ = 0; S_ < nsteps; ++S_) {
+    auto step = [&](int S_) {
         const int r = S_ - w;
         if (nl > 0 && r >= 0 && r < by) {
+            if (r == 0) {
+                // history before this wave's first row: input rows jy0-1 and
+                // jy0-2; level t's input row jy' holds u_t[jy' - t + 1][jx - t + 1]
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    if (l < nl) {
+                        const int t = tl0 + l;
+                        const rsrc_t rr_ = src_of(t);
+                        const int y1 = jy0 - t, y2 = jy0 - t - 1, x = jxl - t;
+                        x1b[l] = ld(rr_, y1, x - 1);
+                        x1a[l] = ld(rr_, y1, x);
+#pragma unroll
+                        for (int c = 0; c < C; ++c) in1[l][c] = ld(rr_, y1, x + 1 + c);
+                        x2a[l] = ld(rr_, y2, x);
+#pragma unroll
+                        for (int c = 0; c < C; ++c) in2[l][c] = ld(rr_, y2, x + 1 + c);
+                    }
+                }
+            }
             const int jy = jy0 + r;
             const int rk = r % K;
             if (rk == 0) {
-                // publish this chunk's left faces to LDS, fetch the next chunk
-                mylfs[2 * lane] = lfp0;
-                mylfs[2 * lane + 1] = lfp1;
+                sm.lfs[w][2 * lane] = lfp0;
+                sm.lfs[w][2 * lane + 1] = lfp1;
                 __builtin_amdgcn_wave_barrier();
                 lf_fetch(r + K);
             }
             // input row of this wave's first level
             A in0[C], x0a, x0b;
-            if (w == 0) {
-                x0b = bpn[0];
-                x0a = bpn[1];
-#pragma unroll
-                for (int c = 0; c < C; ++c) in0[c] = bpn[2 + c];
-                if (r + 1 < by) ldseg<S, BND, C + 2>(bsrc, ny, nx, jy + 1 - t0 + 1, jxl - t0 - 1, bpn);
-            } else {
-                const A* h = hand + ((w - 1) * 2 + ((S_ - 1) & 1)) * ROW;
+            {
+                const A* h = w == 0 ? &sm.bchunk[(r / KB) & 1][r % KB][0] : &sm.hand[w][(S_ - 1) & 1][0];
                 x0b = h[lane * C];
                 x0a = h[lane * C + 1];
 #pragma unroll
@@ -178,7 +223,9 @@ __device__ __forceinline__ void exec_tile(const TiledProblem& P, int kt, int ky,
             for (int l = 0; l < L; ++l) {
                 if (l < nl) {
                     const int t = tl0 + l;
+                    const int y = jy - t;
                     A out[C];
+                    const bool rok = row_ok(y);
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
                         const A cc = c >= 1 ? in1[l][c - 1] : x1a[l];
@@ -187,11 +234,7 @@ __device__ __forceinline__ void exec_tile(const TiledProblem& P, int kt, int ky,
                         const A ee = in1[l][c];
                         const A ww = c >= 2 ? in1[l][c - 2] : (c == 1 ? x1a[l] : x1b[l]);
                         A v = Tr<S>::rnd(jac2(cc, nn, ss, ee, ww));
-                        if (BND) {
-                            const int y = jy - t, x = jxl + c - t;
-                            const bool inside = (y >= 1) & (y <= ny - 2) & (x >= 1) & (x <= nx - 2);
-                            v = inside ? v : cc;
-                        }
+                        if (BND) v = (rok && ((colok >> (l * C + c)) & 1u)) ? v : cc;
                         out[c] = v;
                     }
                     // rotate this level's input history
@@ -203,32 +246,25 @@ __device__ __forceinline__ void exec_tile(const TiledProblem& P, int kt, int ky,
                     x2a[l] = x1a[l];
                     x1a[l] = x0a;
                     x1b[l] = x0b;
-
-                    S* dst = level_dst<S>(P, t);
-                    const int y = jy - t;
                     if (t == ttop || r >= by - 2) {
                         // top plane, or one of the two high rows of this level
-                        S* row = dst + (size_t)(BND ? clampi(y, 0, ny - 1) : y) * nx;
+                        const rsrc_t dr = dst_of(t);
 #pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            const int x = jxl + c - t;
-                            if (!BND || ((y >= 1) & (y <= ny - 2) & (x >= 1) & (x <= nx - 2)))
-                                Tr<S>::st(row + x, out[c]);
-                        }
+                        for (int c = 0; c < C; ++c)
+                            st(dr, y, jxl + c - t, rok && ((colok >> (l * C + c)) & 1u), out[c]);
                     }
                     if (t < ttop) {
-                        const A lfA = mylfs[2 * (rk * L + l) + 1];  // column jx0-1
-                        const A lfB = mylfs[2 * (rk * L + l)];      // column jx0-2
+                        const A lfA = sm.lfs[w][2 * (rk * L + l) + 1];  // column jx0-1
+                        const A lfB = sm.lfs[w][2 * (rk * L + l)];      // column jx0-2
                         x0a = shr1(out[C - 1], lfA);
-                        if constexpr (C >= 2) x0b = shr1(out[C - 2], lfB);
+                        if constexpr (C >= 2) x0b = shr1(out[C >= 2 ? C - 2 : 0], lfB);
                         else x0b = shr1(x0a, lfB);
-                        // stage the two-wide high face (columns jx0+bx-2, jx0+bx-1)
                         if (lane == 63) {
-                            myrfs[2 * (rk * L + l)] = C >= 2 ? out[C >= 2 ? C - 2 : 0] : x0a;
-                            myrfs[2 * (rk * L + l) + 1] = out[C - 1];
+                            sm.rfs[w][2 * (rk * L + l)] = C >= 2 ? out[C >= 2 ? C - 2 : 0] : x0a;
+                            sm.rfs[w][2 * (rk * L + l) + 1] = out[C - 1];
                         }
-                        if (l == L - 1 && w < G - 1) {
-                            A* h = hand + (w * 2 + (S_ & 1)) * ROW;
+                        if (l + 1 == L && w + 1 < G) {
+                            A* h = &sm.hand[w + 1 < G ? w + 1 : 0][S_ & 1][0];
 #pragma unroll
                             for (int c = 0; c < C; ++c) h[2 + lane * C + c] = out[c];
                             if (lane == 0) {
@@ -242,36 +278,278 @@ __device__ __forceinline__ void exec_tile(const TiledProblem& P, int kt, int ky,
                 }
             }
             if (rk == K - 1 || r == by - 1) {
-                // flush the staged high faces of this chunk: lane i -> (row, level)
+                // flush the staged right faces of this chunk: lane i -> (row, level)
                 __builtin_amdgcn_wave_barrier();
                 const int rr = r - rk + lane / L, l = lane % L, t = tl0 + l;
                 if (rr <= r && l < nl && t < ttop) {
-                    S* dst = level_dst<S>(P, t);
-                    const int y = jy0 + rr - t, x = jx0 + bx - 2 - t;
-                    const A v0 = myrfs[2 * lane], v1 = myrfs[2 * lane + 1];
-                    if (!BND) {
-                        Tr<S>::st(dst + (size_t)y * nx + x, v0);
-                        Tr<S>::st(dst + (size_t)y * nx + x + 1, v1);
-                    } else if (y >= 1 && y <= ny - 2) {
-                        if (x >= 1 && x <= nx - 2) Tr<S>::st(dst + (size_t)y * nx + x, v0);
-                        if (x + 1 >= 1 && x + 1 <= nx - 2) Tr<S>::st(dst + (size_t)y * nx + x + 1, v1);
-                    }
+                    const int y = jy0 + rr - t, x = jx0 + 64 * C - 2 - t;
+                    const bool rok = row_ok(y);
+                    const int o0 = (rok && col_ok(x)) ? (y * nx + x) * ES : OOB;
+                    const int o1 = (rok && col_ok(x + 1)) ? (y * nx + x + 1) * ES : OOB;
+                    const A v0 = sm.rfs[w][2 * lane], v1 = sm.rfs[w][2 * lane + 1];
+                    IO<S>::st(rdE, lf_even ? o0 : OOB, v0);
+                    IO<S>::st(rdO, lf_even ? OOB : o0, v0);
+                    IO<S>::st(rdE, lf_even ? o1 : OOB, v1);
+                    IO<S>::st(rdO, lf_even ? OOB : o1, v1);
                 }
                 __builtin_amdgcn_wave_barrier();
             }
         }
-        if constexpr (G > 1) __syncthreads();
+        // bottom-plane staging in block-wide step units: chunk c+1 is loaded
+        // during chunk c and published to LDS at its last step
+        if (S_ % KB == 0 && S_ > 0) chunk_fetch(S_ / KB + 1);
+        if (S_ % KB == KB - 1) chunk_store(S_ / KB + 1);
+        __syncthreads();
+    };
+
+    chunk_fetch(0);
+    if (nl > 0) lf_fetch(0);
+    chunk_store(0);
+    chunk_fetch(1);
+    __syncthreads();
+    const int nsteps = by + G - 1;
+    for (int S_ = 0; S_ < nsteps; ++S_) step(S_);
+}
+
+// Lean path for tiles that hold all bt levels (every tile when bt divides
+// T).  Same dataflow as exec_tile; per-level conditions are compile-time or
+// hoisted to one branch per row step, the two destination buffers are fixed
+// per level parity, and the right-face staging is branch-free.
+template <typename S, int C, int L, int G, bool BND>
+__device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky, int kx,
+                                          Smem<typename Tr<S>::A, C, G>& sm) {
+    using A = typename Tr<S>::A;
+    using CF = Cfg<C, G>;
+    constexpr int ES = sizeof(S);
+    constexpr int ROW = CF::ROW, KB = CF::KB, NPT = CF::NPT;
+    constexpr int K = 64 / L;  // rows per left/right-face chunk
+    const int lane = threadIdx.x & 63;
+    const int w = uni((int)(threadIdx.x >> 6));
+    const int ny = P.n[0], nx = P.n[1], by = P.b[1];
+    const int t0 = kt * (G * L);
+    const int tl0 = t0 + w * L;
+    const int jy0 = 1 + ky * by, jx0 = 1 + kx * (64 * C);
+    const int jxl = jx0 + lane * C;
+    const bool topwave = w == G - 1;  // owns the tile's top level
+    const uint32_t bytes = (uint32_t)ny * (uint32_t)nx * ES;
+    const uintptr_t pin = (uintptr_t)uptr(P.in), pb0 = (uintptr_t)uptr(P.buf0), pb1 = (uintptr_t)uptr(P.buf1);
+    // level tl0+l writes u_{tl0+l+1}: buffer parity (tl0 + l + 1) & 1
+    const rsrc_t rdE = make_rsrc(uptr((const void*)pick(pb0, pb1, tl0 + 1)), bytes);  // even l
+    const rsrc_t rdO = make_rsrc(uptr((const void*)pick(pb0, pb1, tl0)), bytes);      // odd l
+    const rsrc_t rbot = make_rsrc(uptr((const void*)pick(pick(pb0, pb1, t0), pin, t0 == 0)), bytes);
+    auto offs = [&](int y, int x) { return (y * nx + x) * ES; };
+    auto okoff = [&](int y, int x) {  // byte offset, or OOB outside the interior
+        return (!BND || (y >= 1 && y <= ny - 2 && x >= 1 && x <= nx - 2)) ? offs(y, x) : OOB;
+    };
+    auto ldv = [&](rsrc_t r, int y, int x) -> A {
+        if (BND && (y < 0 || y >= ny)) return A(0);
+        return IO<S>::ld(r, offs(y, x));
+    };
+
+    A in1[L][C], in2[L][C], x1a[L], x1b[L], x2a[L];
+    // history before the first row: input rows jy0-1 and jy0-2 of every level;
+    // level t's input row jy' holds u_t[jy' - t + 1][jx - t + 1]
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const int t = tl0 + l;
+        const uintptr_t ps = pick(pick(pb0, pb1, t), pin, t == 0);
+        const rsrc_t rs = make_rsrc(uptr((const void*)ps), bytes);
+        const int y1 = jy0 - t, y2 = jy0 - t - 1, x = jxl - t;
+        x1b[l] = ldv(rs, y1, x - 1);
+        x1a[l] = ldv(rs, y1, x);
+#pragma unroll
+        for (int c = 0; c < C; ++c) in1[l][c] = ldv(rs, y1, x + 1 + c);
+        x2a[l] = ldv(rs, y2, x);
+#pragma unroll
+        for (int c = 0; c < C; ++c) in2[l][c] = ldv(rs, y2, x + 1 + c);
+    }
+    unsigned colok = 0xFFFFFFFFu;  // BND: bit l*C+c = column c of level l is interior
+    if (BND) {
+        colok = 0;
+#pragma unroll
+        for (int l = 0; l < L; ++l)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int x = jxl + c - (tl0 + l);
+                colok |= (x >= 1 && x <= nx - 2) ? (1u << (l * C + c)) : 0u;
+            }
+    }
+
+    // left faces of level tl0+l (its outputs at jx0-2, jx0-1), one chunk of
+    // rows ahead; lane i carries (row r0 + i / L, level i % L).  Both buffers
+    // are read (one offset out of range) so the descriptor stays uniform.
+    // The two candidate loads stay in registers until the chunk is
+    // published: selecting right after the loads would wait for them.
+    A lfE0 = A(0), lfO0 = A(0), lfE1 = A(0), lfO1 = A(0);
+    const int lf_l = lane % L;
+    const bool lf_even = (lf_l & 1) == 0;
+    const bool lf_top = topwave && lf_l == L - 1;  // the tile's top level has no consumer
+    auto lf_fetch = [&](int r0) {
+        const int rr = r0 + lane / L, t = tl0 + lf_l;
+        const int y = jy0 + rr - t, x = jx0 - t - 2;
+        const bool ok = rr < by && !lf_top && (!BND || (y >= 0 && y < ny));
+        const int o = ok ? offs(y, x) : OOB;
+        lfE0 = IO<S>::ld(rdE, lf_even ? o : OOB);
+        lfO0 = IO<S>::ld(rdO, lf_even ? OOB : o);
+        lfE1 = IO<S>::ld(rdE, lf_even ? o + ES : OOB);
+        lfO1 = IO<S>::ld(rdO, lf_even ? OOB : o + ES);
+    };
+    A bst[NPT];
+    auto chunk_fetch = [&](int c) {
+        const int bx0 = jx0 - t0 - 1;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int idx = threadIdx.x + i * 64 * G;
+            const int rr = c * KB + idx / ROW;
+            if ((KB * ROW) % (64 * G) == 0 || idx < KB * ROW)
+                bst[i] = rr < by ? ldv(rbot, jy0 + rr - t0 + 1, bx0 + idx % ROW) : A(0);
+        }
+    };
+    auto chunk_store = [&](int c) {
+        A* dstc = &sm.bchunk[c & 1][0][0];
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int idx = threadIdx.x + i * 64 * G;
+            if ((KB * ROW) % (64 * G) == 0 || idx < KB * ROW) dstc[idx] = bst[i];
+        }
+    };
+    // right-face staging target: lane 63 writes the chunk slot, others a sink
+    A* const rf_base = lane == 63 ? &sm.rfs[w][0] : &sm.junk[w][2 * lane];
+    const int rf_stride = lane == 63 ? 2 : 0;
+
+    // all levels of one row step; TAIL: one of the tile's two last rows, where
+    // every level also writes its row (the two-wide high face)
+    auto levels = [&](auto tail, int S_, int r, int rk) {
+        constexpr bool TAIL = decltype(tail)::value;
+        const int jy = jy0 + r;
+        A in0[C], x0a, x0b;
+        {
+            const A* h = w == 0 ? &sm.bchunk[(r / KB) & 1][r % KB][0] : &sm.hand[w][(S_ - 1) & 1][0];
+            x0b = h[lane * C];
+            x0a = h[lane * C + 1];
+#pragma unroll
+            for (int c = 0; c < C; ++c) in0[c] = h[2 + lane * C + c];
+        }
+        // left faces of every level for this row, read before any LDS write of
+        // the step so that they are off the level-to-level dependency chain
+        A lfa[L], lfb[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            lfa[l] = sm.lfs[w][2 * (rk * L + l) + 1];  // column jx0-1
+            lfb[l] = sm.lfs[w][2 * (rk * L + l)];      // column jx0-2
+        }
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int t = tl0 + l;
+            const int y = jy - t;
+            const bool rok = !BND || (y >= 1 && y <= ny - 2);
+            A out[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const A cc = c >= 1 ? in1[l][c - 1] : x1a[l];
+                const A nn = c >= 1 ? in2[l][c - 1] : x2a[l];
+                const A ss = c >= 1 ? in0[c - 1] : x0a;
+                const A ee = in1[l][c];
+                const A ww = c >= 2 ? in1[l][c - 2] : (c == 1 ? x1a[l] : x1b[l]);
+                A v = Tr<S>::rnd(jac2(cc, nn, ss, ee, ww));
+                if (BND) v = (rok && ((colok >> (l * C + c)) & 1u)) ? v : cc;
+                out[c] = v;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                in2[l][c] = in1[l][c];
+                in1[l][c] = in0[c];
+            }
+            x2a[l] = x1a[l];
+            x1a[l] = x0a;
+            x1b[l] = x0b;
+            const rsrc_t rd = (l & 1) ? rdO : rdE;
+            auto store_row = [&]() {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int x = jxl + c - t;
+                    IO<S>::st(rd, BND ? ((rok && ((colok >> (l * C + c)) & 1u)) ? offs(y, x) : OOB) : offs(y, x), out[c]);
+                }
+            };
+            auto pass_on = [&]() {
+                const A lfA = lfa[l], lfB = lfb[l];
+                x0a = shr1(out[C - 1], lfA);
+                if constexpr (C >= 2) x0b = shr1(out[C >= 2 ? C - 2 : 0], lfB);
+                else x0b = shr1(x0a, lfB);
+                A* rf = rf_base + rf_stride * (rk * L + l);
+                rf[0] = C >= 2 ? out[C >= 2 ? C - 2 : 0] : x0a;
+                rf[1] = out[C - 1];
+                if (TAIL) store_row();
+#pragma unroll
+                for (int c = 0; c < C; ++c) in0[c] = out[c];
+                return std::pair<A, A>(lfA, lfB);
+            };
+            if (l + 1 < L) {
+                pass_on();
+            } else if (!topwave) {
+                const auto lf = pass_on();
+                A* h = &sm.hand[w + 1 < G ? w + 1 : 0][S_ & 1][0];
+#pragma unroll
+                for (int c = 0; c < C; ++c) h[2 + lane * C + c] = out[c];
+                if (lane == 0) {
+                    h[0] = lf.second;
+                    h[1] = lf.first;
+                }
+            } else {
+                store_row();  // top plane
+            }
+        }
+    };
+
+    chunk_fetch(0);
+    lf_fetch(0);
+    chunk_store(0);
+    chunk_fetch(1);
+    __syncthreads();
+    const int nsteps = by + G - 1;
+    for (int S_ = 0; S_ < nsteps; ++S_) {
+        if (S_ % KB == 0 && S_ > 0) {
+            // publish chunk c = S_/KB (loaded during chunk c-1) before any
+            // store of this step, then start loading chunk c+1
+            chunk_store(S_ / KB);
+            __syncthreads();
+            chunk_fetch(S_ / KB + 1);
+        }
+        const int r = S_ - w;
+        if (r >= 0 && r < by) {
+            const int rk = r % K;
+            if (rk == 0) {
+                sm.lfs[w][2 * lane] = lf_even ? lfE0 : lfO0;
+                sm.lfs[w][2 * lane + 1] = lf_even ? lfE1 : lfO1;
+                __builtin_amdgcn_wave_barrier();
+                lf_fetch(r + K);
+            }
+            if (r < by - 2) levels(std::integral_constant<bool, false>{}, S_, r, rk);
+            else levels(std::integral_constant<bool, true>{}, S_, r, rk);
+            if (rk == K - 1 || r == by - 1) {
+                // flush the staged right faces of this chunk: lane i -> (row, level)
+                __builtin_amdgcn_wave_barrier();
+                const int rr = r - rk + lane / L, t = tl0 + lf_l;
+                const int y = jy0 + rr - t, x = jx0 + 64 * C - 2 - t;
+                const bool ok = rr <= r && !lf_top;
+                const rsrc_t r0 = rdE, r1 = rdO;
+                const int o0 = ok ? okoff(y, x) : OOB, o1 = ok ? okoff(y, x + 1) : OOB;
+                const A v0 = sm.rfs[w][2 * lane], v1 = sm.rfs[w][2 * lane + 1];
+                IO<S>::st(r0, lf_even ? o0 : OOB, v0);
+                IO<S>::st(r1, lf_even ? OOB : o0, v0);
+                IO<S>::st(r0, lf_even ? o1 : OOB, v1);
+                IO<S>::st(r1, lf_even ? OOB : o1, v1);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
     }
 }
 
 template <typename S, int C, int L, int G>
 __global__ void __launch_bounds__(64 * G) k_tiled2d(TiledLaunch Lc) {
     using A = typename Tr<S>::A;
-    __shared__ A hand[(G > 1 ? G - 1 : 1) * 2 * (64 * C + 2)];
-    __shared__ A lfs[G * 128];
-    __shared__ A rfs[G * 128];
-    __shared__ int s_tk;
-    __shared__ int s_go;
+    __shared__ Smem<A, C, G> sm;
     // One block per queue entry.  The tile is the block's ticket, not its
     // blockIdx: tickets are handed out in the order blocks start, so every
     // predecessor of a ticket was taken earlier by a block that is running,
@@ -279,10 +557,10 @@ __global__ void __launch_bounds__(64 * G) k_tiled2d(TiledLaunch Lc) {
     // thread-0 regions below is lowered into per-lane loops that deadlock.)
     const int wave = uni((int)(threadIdx.x >> 6));
     if (threadIdx.x == 0)
-        s_tk = (int)__hip_atomic_fetch_add(Lc.hdr + HDR_TICKET, 1u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+        sm.tk = (int)__hip_atomic_fetch_add(Lc.hdr + HDR_TICKET, 1u, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const int tk = uni(s_tk);
+    const int tk = uni(sm.tk);
     if (tk >= Lc.nq) return;
     const QEntry e = Lc.queue[tk];
     const int pi = Lc.qprob ? uni((int)Lc.qprob[tk]) : 0;
@@ -295,18 +573,23 @@ __global__ void __launch_bounds__(64 * G) k_tiled2d(TiledLaunch Lc) {
         for (int m = 1; m < 8; ++m)
             need += leaf_nonempty(P, kt - ((m >> 2) & 1), ky - ((m >> 1) & 1), kx - (m & 1));
         const bool go = wait_ready(cnt, need, Lc.hdr, Lc.limit_ticks);
-        if (threadIdx.x == 0) s_go = go ? 1 : 0;
+        if (threadIdx.x == 0) sm.go = go ? 1 : 0;
     }
     __syncthreads();
-    const int go = uni(s_go);
+    const int go = uni(sm.go);
     // every wave acquires: the barrier alone does not order its loads after
     // another wave's cache invalidation
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (go) {
-        if (leaf_interior(P, kt, ky, kx))
-            exec_tile<S, C, L, G, false>(P, kt, ky, kx, hand, lfs, rfs);
-        else
-            exec_tile<S, C, L, G, true>(P, kt, ky, kx, hand, lfs, rfs);
+        const bool full = (kt + 1) * P.b[0] <= P.T && P.b[0] == G * L;
+        if (full) {
+            if (leaf_interior(P, kt, ky, kx))
+                exec_full<S, C, L, G, false>(P, kt, ky, kx, sm);
+            else
+                exec_full<S, C, L, G, true>(P, kt, ky, kx, sm);
+        } else {
+            exec_tile<S, C, L, G, true>(P, kt, ky, kx, sm);
+        }
     }
     // every wave releases its own stores (the barrier does not wait for
     // outstanding vector-memory stores), then one thread signals
@@ -323,18 +606,18 @@ __global__ void __launch_bounds__(64 * G) k_tiled2d(TiledLaunch Lc) {
 }
 
 template <typename S, int C, int L, int G>
-hipError_t launch_inst(const TiledLaunch& Lc, int, hipStream_t s) {
+hipError_t launch_inst(const TiledLaunch& Lc, hipStream_t s) {
     if (Lc.nq <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_tiled2d<S, C, L, G>), dim3(Lc.nq), dim3(64 * G), 0, s, Lc);
     return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_dtype(const int* b, const TiledLaunch& Lc, int grid_cap, hipStream_t s) {
+hipError_t launch_dtype(const int* b, const TiledLaunch& Lc, hipStream_t s) {
     const int C = b[2] / 64;
     const int bt = b[0];
 #define PCOT_TL(CC, LL, GG) \
-    if (C == CC && bt <= LL * GG) return launch_inst<S, CC, LL, GG>(Lc, grid_cap, s);
+    if (C == CC && bt <= LL * GG) return launch_inst<S, CC, LL, GG>(Lc, s);
     // levels per wave: 8 for 1-2 columns per lane, 4 for 4 (register budget)
     PCOT_TL(1, 4, 1) PCOT_TL(1, 8, 1) PCOT_TL(1, 8, 2) PCOT_TL(1, 8, 4) PCOT_TL(1, 8, 8)
     PCOT_TL(2, 4, 1) PCOT_TL(2, 8, 1) PCOT_TL(2, 8, 2) PCOT_TL(2, 8, 4) PCOT_TL(2, 8, 8)
@@ -353,11 +636,11 @@ bool tiled2d_supported(const int* b) {
     return true;
 }
 
-hipError_t launch_tiled2d(int dtype, const int* b, const TiledLaunch& Lc, int grid_cap, hipStream_t s) {
+hipError_t launch_tiled2d(int dtype, const int* b, const TiledLaunch& Lc, int, hipStream_t s) {
     switch (dtype) {
-        case 0: return launch_dtype<double>(b, Lc, grid_cap, s);
-        case 1: return launch_dtype<float>(b, Lc, grid_cap, s);
-        default: return launch_dtype<uint16_t>(b, Lc, grid_cap, s);
+        case 0: return launch_dtype<double>(b, Lc, s);
+        case 1: return launch_dtype<float>(b, Lc, s);
+        default: return launch_dtype<uint16_t>(b, Lc, s);
     }
 }
 
