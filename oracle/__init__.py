@@ -207,23 +207,24 @@ def cot_leaves(dims, T, tile, parallel_groups=False):
     dimension (the others are already at leaf size, so halving them would
     give zero-width orthants, which are skipped); orthants containing no
     domain point are skipped; leaves are visited in lexicographic orthant
-    order (time bit most significant).  With parallel_groups, orthants of one
-    split are visited grouped by their number of upper halves (the wavefronts
-    that are separated by a taskwait in the parallel version), lexicographic
-    within a group.  Returns leaf origins as tile-grid indices.
+    order (time bit most significant).
+
+    parallel_groups: the parallel version runs the orthants of one split as
+    tasks grouped by their number of upper halves, with a taskwait between
+    groups; the orthants of a group run concurrently.  Their leaf sequences
+    are therefore merged round-robin (one leaf of each member in turn), and
+    groups follow each other.  Returns leaf origins as tile-grid indices.
     """
     lo, hi = skewed_bbox(dims, T)
     size = [padded_extent(h - l + 1, b) for l, h, b in zip(lo, hi, tile)]
-    out = []
 
     def rec(org, sz):
         if any(s <= 0 for s in sz):
-            return
+            return []
         if not box_has_domain_point(org, sz, dims, T):
-            return
+            return []
         if all(s <= b for s, b in zip(sz, tile)):
-            out.append(tuple((o - l) // b for o, l, b in zip(org, lo, tile)))
-            return
+            return [tuple((o - l) // b for o, l, b in zip(org, lo, tile))]
         halves = []
         for o, s, b in zip(org, sz, tile):
             if s > b:
@@ -232,14 +233,25 @@ def cot_leaves(dims, T, tile, parallel_groups=False):
             else:
                 halves.append([(o, s), (o + s, 0)])
         children = list(product(*[range(2)] * len(sz)))
-        if parallel_groups:
-            children.sort(key=lambda bits: (sum(bits), bits))
-        for bits in children:
-            rec([halves[d][bits[d]][0] for d in range(len(sz))],
-                [halves[d][bits[d]][1] for d in range(len(sz))])
 
-    rec(lo, size)
-    return out
+        def child(bits):
+            return rec([halves[d][bits[d]][0] for d in range(len(sz))],
+                       [halves[d][bits[d]][1] for d in range(len(sz))])
+
+        out = []
+        if not parallel_groups:
+            for bits in children:
+                out += child(bits)
+            return out
+        for g in range(len(sz) + 1):
+            seqs = [child(bits) for bits in children if sum(bits) == g]
+            for i in range(max([len(q) for q in seqs] + [0])):
+                for q in seqs:
+                    if i < len(q):
+                        out.append(q[i])
+        return out
+
+    return rec(lo, size)
 
 
 def slt_leaves(dims, T, tile, wavefront=False):

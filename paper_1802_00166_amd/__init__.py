@@ -52,6 +52,8 @@ _SIGS = {
     "pcot_stream_status": (_I32, [_P, _P]),
     "pcot_last_error": (ctypes.c_char_p, []),
     "pcot_version": (ctypes.c_char_p, []),
+    "pcot_dp_workspace": (_SZ, [_I64, _TP, _I32]),
+    "pcot_dp_run": (_I32, [_P, _I64, _I64, _TP, _I32, _P, _P, _SZ, _P]),
     "pcot_kernel_timing": (_I32, [_I32]),
     "pcot_kernel_timing_read": (_I32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -161,6 +163,34 @@ def kernel_timing_read():
 def tile_supported(kind: str, dtype: str, tile) -> bool:
     tp = tile if isinstance(tile, pcot_tile) else make_tile(*tile)
     return pcot_stencil_tile_supported(KINDS[kind], DTYPES[dtype], ctypes.byref(tp)) == 0
+
+
+def dp_workspace_bytes(N: int, tile=(0, 64, 64, 256), schedule: str = "slt_wave") -> int:
+    tp = tile if isinstance(tile, pcot_tile) else make_tile(*tile)
+    n = pcot_dp_workspace(int(N), ctypes.byref(tp), SCHEDULES[schedule])
+    if n == 0:
+        raise PcotError(-1, last_error())
+    return int(n)
+
+
+def dp_run(p, pmax: int, tile=(0, 64, 64, 256), schedule: str = "slt_wave", out=None, workspace=None,
+           stream=None):
+    """Matrix-chain DP on device int64 tensor p (N+1 dims); returns the N x N int64 cost matrix.
+
+    tile = (unused, b, b, k-chunk)."""
+    torch = _torch()
+    assert p.is_cuda and p.dtype == torch.int64 and p.is_contiguous()
+    N = p.numel() - 1
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.int64, device=p.device)
+    tp = tile if isinstance(tile, pcot_tile) else make_tile(*tile)
+    nbytes = dp_workspace_bytes(N, tp, schedule)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = alloc_workspace(nbytes, p.device)
+    check(pcot_dp_run(ctypes.c_void_p(p.data_ptr()), int(N), int(pmax), ctypes.byref(tp), SCHEDULES[schedule],
+                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                      ctypes.c_size_t(workspace.numel()), stream_ptr(stream)))
+    return out
 
 
 def plan(kind: str, shape, T: int, tile, schedule: str):

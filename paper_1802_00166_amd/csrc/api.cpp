@@ -22,6 +22,21 @@ bool tiled1d_supported(const int* b);
 hipError_t launch_tiled1d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
 bool tiled3d_supported(const int* b);
 hipError_t launch_tiled3d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
+struct DPLaunch {
+    const long long* p;
+    void* Cw;
+    long long* C;
+    int N, Nout, b;
+    const int2* tiles;
+    int ntiles;
+    const int4* items;
+    int nitems;
+    unsigned* hdr;
+    long long pmax;
+};
+bool dp_block_supported(int b);
+hipError_t launch_dp_phase(bool wide, const DPLaunch& a, bool init, hipStream_t s);
+hipError_t launch_dp_pad(const long long* p, long long* pp, int Nout, int N, hipStream_t s);
 }  // namespace pcot
 
 using namespace pcot;
@@ -241,6 +256,146 @@ pcot_status timed_launch_end(hipStream_t s, hipEvent_t stop) {
     return PCOT_OK;
 }
 
+// --------------------------------------------------------------- DP plans ---
+// Phases of (I, J) tiles over the upper triangle of nT x nT tiles; every tile's
+// operands lie in tiles of earlier phases or in the tile itself.
+//   wavefront: phase d = tile diagonal J - I = d;
+//   recursive: a triangle splits into its two half triangles (concurrent,
+//   merged phase by phase) followed by the square between them; a square
+//   splits into bottom-left, then top-left and bottom-right (concurrent), then
+//   top-right (the orthant recursion of Section 4.2 applied to the tile
+//   triangle, with the parallel version's wavefront grouping).
+using Phases = std::vector<std::vector<std::pair<int, int>>>;
+
+void merge_into(Phases& dst, size_t at, const Phases& src) {
+    if (dst.size() < at + src.size()) dst.resize(at + src.size());
+    for (size_t k = 0; k < src.size(); ++k)
+        dst[at + k].insert(dst[at + k].end(), src[k].begin(), src[k].end());
+}
+
+Phases dp_square(int i0, int j0, int n) {  // rows [i0, i0+n), cols [j0, j0+n)
+    if (n == 1) return Phases{{{i0, j0}}};
+    const int h = n / 2, r = n - h;
+    // bottom-left: rows [i0+h, i0+n), cols [j0, j0+h)
+    Phases out;
+    Phases bl = dp_square(i0 + h, j0, std::min(h, r));
+    (void)r;
+    merge_into(out, 0, bl);
+    Phases mid;
+    merge_into(mid, 0, dp_square(i0, j0, h));
+    merge_into(mid, 0, dp_square(i0 + h, j0 + h, h));
+    merge_into(out, out.size(), mid);
+    merge_into(out, out.size(), dp_square(i0, j0 + h, h));
+    return out;
+}
+
+Phases dp_triangle(int i0, int n) {  // tiles (I, J), i0 <= I <= J < i0+n
+    if (n == 1) return Phases{{{i0, i0}}};
+    const int h = n / 2;
+    Phases out;
+    merge_into(out, 0, dp_triangle(i0, h));
+    merge_into(out, 0, dp_triangle(i0 + h, h));
+    merge_into(out, out.size(), dp_square(i0, i0 + h, h));
+    return out;
+}
+
+struct DPPlan {
+    int nT = 0, b = 0, kc = 0;
+    std::vector<int> tile_off, item_off;  // per phase, into the arrays below
+    std::vector<int2> tiles;
+    std::vector<int4> items;
+    int2* dtiles = nullptr;
+    int4* ditems = nullptr;
+    ~DPPlan() {
+        if (dtiles) (void)hipFree(dtiles);
+        if (ditems) (void)hipFree(ditems);
+    }
+};
+std::map<std::vector<int64_t>, std::unique_ptr<DPPlan>> g_dp_plans;
+
+pcot_status get_dp_plan(int nT, int b, int kc, int sched, DPPlan** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::vector<int64_t> key = {dev, nT, b, kc, sched};
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dp_plans.find(key);
+    if (it != g_dp_plans.end()) { *out = it->second.get(); return PCOT_OK; }
+    Phases ph;
+    if (sched == PCOT_SLT_WAVE) {
+        ph.resize(nT);
+        for (int d = 0; d < nT; ++d)
+            for (int I = 0; I + d < nT; ++I) ph[d].push_back({I, I + d});
+    } else {
+        int p2 = 1;
+        while (p2 < nT) p2 *= 2;
+        // recursion over the padded power-of-two triangle, tiles past nT dropped
+        Phases full = dp_triangle(0, p2);
+        for (auto& q : full) {
+            std::vector<std::pair<int, int>> keep;
+            for (auto& t : q)
+                if (t.second < nT) keep.push_back(t);
+            if (!keep.empty()) ph.push_back(keep);
+        }
+    }
+    auto P = std::make_unique<DPPlan>();
+    P->nT = nT; P->b = b; P->kc = kc;
+    for (auto& q : ph) {
+        P->tile_off.push_back((int)P->tiles.size());
+        P->item_off.push_back((int)P->items.size());
+        for (auto& t : q) {
+            const int ti = (int)P->tiles.size() - P->tile_off.back();
+            P->tiles.push_back(int2{t.first, t.second});
+            if (t.second > t.first) {
+                const int k0 = (t.first + 1) * b - 1, k1 = t.second * b;  // external [k0, k1)
+                for (int k = k0; k < k1; k += kc) P->items.push_back(int4{ti, k, std::min(k + kc, k1), 0});
+            }
+        }
+    }
+    P->tile_off.push_back((int)P->tiles.size());
+    P->item_off.push_back((int)P->items.size());
+    HIP_TRY(hipMalloc(&P->dtiles, sizeof(int2) * std::max<size_t>(1, P->tiles.size())));
+    HIP_TRY(hipMemcpy(P->dtiles, P->tiles.data(), sizeof(int2) * P->tiles.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&P->ditems, sizeof(int4) * std::max<size_t>(1, P->items.size())));
+    if (!P->items.empty())
+        HIP_TRY(hipMemcpy(P->ditems, P->items.data(), sizeof(int4) * P->items.size(), hipMemcpyHostToDevice));
+    *out = P.get();
+    g_dp_plans.emplace(key, std::move(P));
+    return PCOT_OK;
+}
+
+struct DPArgs {
+    int64_t N = 0, Np = 0;
+    int b = 64, kc = 256;
+    bool wide = false;
+    size_t hdr = 0, pp = 0, cw = 0, total = 0;
+};
+
+pcot_status dp_validate(int64_t N, int64_t pmax, const pcot_tile* tile, int32_t schedule, DPArgs& A) {
+    if (N < 1 || N > 65536) return fail(PCOT_ERR_INVALID, "N=%lld out of range 1..65536", (long long)N);
+    if (schedule != PCOT_SLT_WAVE && schedule != PCOT_COT_PAR)
+        return fail(PCOT_ERR_INVALID, "DP schedules: PCOT_SLT_WAVE or PCOT_COT_PAR");
+    A.N = N;
+    if (tile) {
+        A.b = tile->s[0];
+        A.kc = tile->s[2] > 0 ? tile->s[2] : 256;
+        if (tile->s[1] != tile->s[0]) return fail(PCOT_ERR_INVALID, "DP tiles are square: s[0] == s[1]");
+    }
+    if (!dp_block_supported(A.b)) return fail(PCOT_ERR_UNSUPPORTED, "DP block size %d (supported: 32, 64)", A.b);
+    if (A.kc < 16 || A.kc % 16) return fail(PCOT_ERR_INVALID, "DP k-chunk %d: multiple of 16 required", A.kc);
+    A.Np = (N + A.b - 1) / A.b * A.b;
+    // exactness: every candidate is at most (N-1) * pmax^3
+    const long double bound = (long double)(N > 1 ? N - 1 : 1) * (long double)pmax * pmax * pmax;
+    if (pmax < 1) return fail(PCOT_ERR_INVALID, "pmax=%lld < 1", (long long)pmax);
+    if (bound >= 4611686018427387904.0L) return fail(PCOT_ERR_OVERFLOW, "(N-1)*pmax^3 >= 2^62");
+    A.wide = bound >= 4294967296.0L;
+    const size_t es = A.wide ? 8 : 4;
+    A.hdr = 0;
+    A.pp = align_up(HDR_WORDS * sizeof(unsigned));
+    A.cw = A.pp + align_up(sizeof(int64_t) * (A.Np + 1));
+    A.total = A.cw + align_up(es * (size_t)A.Np * A.Np);
+    return PCOT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -351,6 +506,52 @@ pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, i
     st = timed_launch_begin(s, &stop);
     if (st != PCOT_OK) return st;
     HIP_TRY(launch_tiled_kind(kind, dtype, p.b, L, 0, s));
+    return timed_launch_end(s, stop);
+}
+
+size_t pcot_dp_workspace(int64_t N, const pcot_tile* tile, int32_t schedule) {
+    DPArgs A;
+    // the 64-bit working matrix is the larger case; size for it
+    if (dp_validate(N, 1, tile, schedule, A) != PCOT_OK) return 0;
+    return A.cw + align_up(8 * (size_t)A.Np * A.Np);
+}
+
+pcot_status pcot_dp_run(const int64_t* p, int64_t N, int64_t pmax, const pcot_tile* tile, int32_t schedule,
+                        int64_t* C, void* workspace, size_t ws_bytes, void* stream) {
+    DPArgs A;
+    pcot_status st = dp_validate(N, pmax, tile, schedule, A);
+    if (st != PCOT_OK) return st;
+    if (!p || !C) return fail(PCOT_ERR_INVALID, "p/C is NULL");
+    if (!workspace || ws_bytes < A.total) return fail(PCOT_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, A.total);
+    if (((uintptr_t)workspace) % ALIGN) return fail(PCOT_ERR_INVALID, "workspace not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    DPPlan* plan = nullptr;
+    st = get_dp_plan((int)(A.Np / A.b), A.b, A.kc, schedule, &plan);
+    if (st != PCOT_OK) return st;
+    DPLaunch L;
+    memset(&L, 0, sizeof L);
+    L.p = (const long long*)(ws + A.pp);
+    L.Cw = ws + A.cw;
+    L.C = (long long*)C;
+    L.N = (int)A.Np;
+    L.Nout = (int)N;
+    L.b = A.b;
+    L.hdr = (unsigned*)(ws + A.hdr);
+    L.pmax = pmax;
+    HIP_TRY(launch_fill_u32(L.hdr, HDR_WORDS, 0u, s));
+    HIP_TRY(launch_dp_pad((const long long*)p, (long long*)(ws + A.pp), (int)N, (int)A.Np, s));
+    HIP_TRY(launch_dp_phase(A.wide, L, true, s));
+    hipEvent_t stop;
+    st = timed_launch_begin(s, &stop);
+    if (st != PCOT_OK) return st;
+    for (size_t q = 0; q + 1 < plan->tile_off.size(); ++q) {
+        L.tiles = plan->dtiles + plan->tile_off[q];
+        L.ntiles = plan->tile_off[q + 1] - plan->tile_off[q];
+        L.items = plan->ditems + plan->item_off[q];
+        L.nitems = plan->item_off[q + 1] - plan->item_off[q];
+        HIP_TRY(launch_dp_phase(A.wide, L, false, s));
+    }
     return timed_launch_end(s, stop);
 }
 

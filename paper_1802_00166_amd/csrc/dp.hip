@@ -1,0 +1,260 @@
+// Interval DP (matrix chain / optimal parenthesization) on b x b tiles of the
+// upper triangle of C:
+//   C[i][i] = 0,  C[i][j] = min_{i<=k<j} C[i][k] + C[k+1][j] + p[i-1] p[k] p[j]
+// (0-based cells here: cell (a, c) covers A_{a+1}..A_{c+1}; its weight for
+// split k' in [a, c) is p[a] * p[k'+1] * p[c+1]).
+//
+// The reduction over k is reordered freely (the Guibas-Kung-Thompson
+// reordering that makes all three dimensions of the OSP nest tileable,
+// Section 5.1.2): integer min and + are exact, so every order and every split
+// of the k range gives the same bits.  For tile (I, J), a split k belongs to
+//   * the external range [(I+1)b-1, Jb-1]: both operands lie in tiles that a
+//     previous phase finished -> min-plus product of complete tiles
+//     (k_ext), split over blocks, combined with atomicMin;
+//   * the internal ranges [i, (I+1)b-2] and [Jb, j-1]: one operand lies in
+//     tile (I, J) itself, below or left of the cell -> k_fin processes the
+//     tile's cells by anti-diagonals after the external part is complete.
+// A diagonal tile (I, I) has only internal splits.
+//
+// 32-bit path: exact while (N-1) * pmax^3 < 2^32, since every candidate is at
+// most (j-i) * pmax^3; the weight is p[a]*p[c+1] (< 2^24) times p[k'+1]
+// (< 2^24), one v_mad_u32_u24.  64-bit path otherwise.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pcot {
+
+struct DPLaunch {
+    const long long* p;  // N+1 dimensions (device)
+    void* Cw;            // working matrix, N x N, u32 or i64 (device)
+    long long* C;        // output, Nout x Nout int64 (device)
+    int N, Nout, b;      // N: padded to a multiple of b (dims past Nout are 1)
+    const int2* tiles;   // (I, J) of the phase (device)
+    int ntiles;
+    const int4* items;   // external work items: (tile index, k_begin, k_end, 0)
+    int nitems;
+    unsigned* hdr;
+    long long pmax;
+};
+
+namespace {
+
+template <typename V> struct DV;
+template <> struct DV<unsigned> {
+    static constexpr unsigned INF = 0xFFFFFFFFu;
+    static __device__ __forceinline__ unsigned madw(unsigned w, unsigned pk, unsigned a) {
+        return __umul24(w, pk) + a;  // w, pk < 2^24: one v_mad_u32_u24
+    }
+    static __device__ __forceinline__ void amin(unsigned* p, unsigned v) { atomicMin(p, v); }
+};
+template <> struct DV<long long> {
+    static constexpr long long INF = 0x7FFFFFFFFFFFFFFFLL;
+    static __device__ __forceinline__ long long madw(long long w, long long pk, long long a) { return w * pk + a; }
+    static __device__ __forceinline__ void amin(long long* p, long long v) { atomicMin(p, v); }
+};
+
+// ---------------------------------------------------------------- setup ---
+// p' = p[0..Nout], then 1 up to index N (padding matrices of 1 x 1 at the end
+// of the chain: a cell (i, j) only reads splits k < j, so real cells never
+// see them).
+__global__ void k_dp_pad(const long long* p, long long* pp, int Nout, int N) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= N; i += gridDim.x * blockDim.x)
+        pp[i] = i <= Nout ? p[i] : 1;
+}
+
+// Cw: off-diagonal upper cells INF, diagonal 0; C: 0 everywhere (the lower
+// triangle stays 0).  Checks 1 <= p <= pmax.
+template <typename V>
+__global__ void k_dp_init(DPLaunch a) {
+    const size_t n = (size_t)a.N * a.N;
+    V* Cw = (V*)a.Cw;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / a.N), c = (int)(e % a.N);
+        Cw[e] = r < c ? DV<V>::INF : (V)0;
+        if (r < a.Nout && c < a.Nout) a.C[(size_t)r * a.Nout + c] = 0;
+    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= a.N; i += gridDim.x * blockDim.x) {
+        const long long v = a.p[i];
+        if (i <= a.Nout && (v < 1 || v > a.pmax))
+            __hip_atomic_store(a.hdr + HDR_ERROR, DEVERR_INPUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ------------------------------------------------------- external part ---
+// One block per work item: a B x B output tile, k in [k0, k1).  Each thread
+// owns an R x R micro-tile; operand tiles go through LDS in KT-deep slices
+// (A transposed so a thread's R rows are contiguous).
+template <typename V, int B, int R>
+__global__ void __launch_bounds__(256) k_dp_ext(DPLaunch a) {
+    constexpr int KT = 16;
+    constexpr int TPR = B / R;  // threads per row of micro-tiles (TPR*TPR == 256)
+    static_assert(TPR * TPR == 256, "micro-tile layout");
+    __shared__ V As[KT][B];     // As[kk][r] = C[I*B + r][k0 + kk]
+    __shared__ V Bs[KT][B];     // Bs[kk][c] = C[k0 + kk + 1][J*B + c]
+    __shared__ V Ps[KT];        // p[k + 1]
+    const int4 it = a.items[blockIdx.x];
+    const int2 tj = a.tiles[it.x];
+    const int I = tj.x, J = tj.y;
+    const int N = a.N;
+    const V* Cw = (const V*)a.Cw;
+    const int tid = threadIdx.x;
+    const int tr = tid / TPR, tc = tid % TPR;  // micro-tile coordinates
+    const int row0 = I * B + tr * R, col0 = J * B + tc * R;
+    V w[R][R], m[R][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            w[r][c] = (V)a.p[row0 + r] * (V)a.p[col0 + c + 1];
+            m[r][c] = DV<V>::INF;
+        }
+    for (int k0 = it.y; k0 < it.z; k0 += KT) {
+        // stage KT columns of the row panel and KT rows of the column panel
+        for (int e = tid; e < KT * B; e += 256) {
+            const int kk = e / B, x = e % B;
+            const int k = k0 + kk;
+            const bool ok = k < it.z;
+            // past the end of the range: a candidate of INF, which never wins
+            As[kk][x] = ok ? Cw[(size_t)(I * B + x) * N + k] : DV<V>::INF;
+            Bs[kk][x] = ok ? Cw[(size_t)(k + 1) * N + J * B + x] : (V)0;
+        }
+        if (tid < KT) Ps[tid] = (k0 + tid < it.z) ? (V)a.p[k0 + tid + 1] : (V)0;
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KT; ++kk) {
+            V av[R], bv[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) av[r] = As[kk][tr * R + r];
+#pragma unroll
+            for (int c = 0; c < R; ++c) bv[c] = Bs[kk][tc * R + c];
+            const V pk = Ps[kk];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const V q = DV<V>::madw(w[r][c], pk, av[r]) + bv[c];
+                    m[r][c] = q < m[r][c] ? q : m[r][c];
+                }
+        }
+        __syncthreads();
+    }
+    V* Cm = (V*)a.Cw;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < R; ++c) DV<V>::amin(Cm + (size_t)(row0 + r) * N + col0 + c, m[r][c]);
+}
+
+// -------------------------------------------------------- finishing part ---
+// One block per tile.  Cells are taken by anti-diagonals of (u, v) =
+// ((I+1)B-1-i, j-JB): a cell's internal operands lie below it (same column)
+// or left of it (same row), i.e. on earlier anti-diagonals.  Each cell is
+// handled by TPC threads that split its internal k range, then min-reduce.
+template <typename V, int B>
+__global__ void __launch_bounds__(256) k_dp_fin(DPLaunch a) {
+    constexpr int TPC = 256 / B;  // threads per cell
+    __shared__ V T[B][B + 1];     // tile (I, J)
+    __shared__ V DI[B][B + 1];    // tile (I, I) (unused when I == J)
+    __shared__ V DJ[B][B + 1];    // tile (J, J) (unused when I == J)
+    __shared__ V red[256];
+    const int2 tj = a.tiles[blockIdx.x];
+    const int I = tj.x, J = tj.y;
+    const int N = a.N;
+    V* Cw = (V*)a.Cw;
+    const int tid = threadIdx.x;
+    const bool diag = I == J;
+    for (int e = tid; e < B * B; e += 256) {
+        const int r = e / B, c = e % B;
+        T[r][c] = Cw[(size_t)(I * B + r) * N + J * B + c];
+        if (!diag) {
+            DI[r][c] = Cw[(size_t)(I * B + r) * N + I * B + c];
+            DJ[r][c] = Cw[(size_t)(J * B + r) * N + J * B + c];
+        }
+    }
+    __syncthreads();
+    // operand lookups in global cell coordinates
+    auto at = [&](int gi, int gk) -> V {  // C[gi][gk]
+        const int bi = gi / B, bk = gk / B;
+        const int li = gi - bi * B, lk = gk - bk * B;
+        if (diag) return T[li][lk];
+        if (bi == I && bk == I) return DI[li][lk];
+        if (bi == J && bk == J) return DJ[li][lk];
+        return T[li][lk];  // (I, J)
+    };
+    const int cell = tid / TPC, part = tid % TPC;
+    for (int s = 0; s <= 2 * B - 2; ++s) {
+        // cell index along the anti-diagonal: u from max(0, s-B+1)
+        const int u = (s < B ? 0 : s - B + 1) + cell;
+        const int v = s - u;
+        const bool act = u < B && v >= 0 && v < B && u <= s;
+        V best = DV<V>::INF;
+        int i = 0, j = 0;
+        if (act) {
+            i = (I + 1) * B - 1 - u;
+            j = J * B + v;
+            if (i < j) {
+                const V wij = (V)a.p[i];
+                const V wj = (V)a.p[j + 1];
+                const int kA0 = i, kA1 = diag ? j : (I + 1) * B - 1;  // [kA0, kA1)
+                const int kB0 = diag ? j : J * B, kB1 = j;            // [kB0, kB1)
+                const int n1 = kA1 - kA0, n = n1 + (kB1 - kB0);
+                for (int q = part; q < n; q += TPC) {
+                    const int k = q < n1 ? kA0 + q : kB0 + (q - n1);
+                    const V cand = at(i, k) + at(k + 1, j) + wij * (V)a.p[k + 1] * wj;
+                    best = cand < best ? cand : best;
+                }
+            }
+        }
+        red[tid] = best;
+        __syncthreads();
+        if (act && part == 0 && i < j) {
+            V mm = T[i - I * B][j - J * B];  // external minimum (INF on diagonal tiles)
+            for (int q = 0; q < TPC; ++q) mm = red[tid + q] < mm ? red[tid + q] : mm;
+            T[i - I * B][j - J * B] = mm;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < B * B; e += 256) {
+        const int r = e / B, c = e % B;
+        const int gi = I * B + r, gj = J * B + c;
+        if (gi <= gj) {
+            const V v = T[r][c];
+            Cw[(size_t)gi * N + gj] = v;
+            if (gj < a.Nout) a.C[(size_t)gi * a.Nout + gj] = (long long)v;
+        }
+    }
+}
+
+template <typename V, int B>
+hipError_t launch_phase_t(const DPLaunch& a, bool init, hipStream_t s) {
+    if (init) {
+        hipLaunchKernelGGL((k_dp_init<V>), dim3(2048), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    constexpr int R = B == 32 ? 2 : (B == 64 ? 4 : 8);
+    if (a.nitems > 0) hipLaunchKernelGGL((k_dp_ext<V, B, R>), dim3(a.nitems), dim3(256), 0, s, a);
+    if (a.ntiles > 0) hipLaunchKernelGGL((k_dp_fin<V, B>), dim3(a.ntiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool dp_block_supported(int b) { return b == 32 || b == 64; }
+
+hipError_t launch_dp_pad(const long long* p, long long* pp, int Nout, int N, hipStream_t s) {
+    hipLaunchKernelGGL(k_dp_pad, dim3((N + 256) / 256), dim3(256), 0, s, p, pp, Nout, N);
+    return hipGetLastError();
+}
+
+// One phase: external items then the finishing pass of the phase's tiles
+// (or, with init, the initialisation of the working matrices).
+hipError_t launch_dp_phase(bool wide, const DPLaunch& a, bool init, hipStream_t s) {
+    if (!wide) {
+        if (a.b == 32) return launch_phase_t<unsigned, 32>(a, init, s);
+        return launch_phase_t<unsigned, 64>(a, init, s);
+    }
+    if (a.b == 32) return launch_phase_t<long long, 32>(a, init, s);
+    return launch_phase_t<long long, 64>(a, init, s);
+}
+
+}  // namespace pcot

@@ -82,6 +82,11 @@ void slt(const StencilGeom& g, std::vector<Leaf>& out) {
 // the leaf in some dimension is halved there; in dimensions already at leaf
 // size the second half has zero width and is skipped (zero-orthant exit);
 // orthants without a domain point are skipped (empty-orthant exit).
+// Sequential: orthants in lexicographic order.  Grouped (the parallel
+// version): orthants with the same number of upper halves form one group of
+// concurrent tasks, groups are separated by a taskwait; a group's concurrent
+// execution is serialised into the queue by merging its members' leaf
+// sequences round-robin.
 void cot_rec(const StencilGeom& g, const int64_t* org, const int64_t* sz, bool grouped,
              std::vector<Leaf>& out) {
     const int D = g.d + 1;
@@ -106,25 +111,33 @@ void cot_rec(const StencilGeom& g, const int64_t* org, const int64_t* sz, bool g
             h[i][1][0] = org[i] + sz[i]; h[i][1][1] = 0;
         }
     }
-    const int nch = 1 << D;
-    int order[16];
-    for (int m = 0; m < nch; ++m) order[m] = m;  // bit D-1-i of m = half of dim i
-    if (grouped)
-        std::stable_sort(order, order + nch,
-                         [](int a, int b) { return __builtin_popcount(a) < __builtin_popcount(b); });
-    for (int c = 0; c < nch; ++c) {
-        const int m = order[c];
+    const int nch = 1 << D;  // bit D-1-i of a child index = half of dim i
+    auto child = [&](int m, std::vector<Leaf>& dst) {
         int64_t o2[4], s2[4];
         for (int i = 0; i < D; ++i) {
             const int bit = (m >> (D - 1 - i)) & 1;
             o2[i] = h[i][bit][0];
             s2[i] = h[i][bit][1];
+            if (s2[i] == 0) return;  // zero orthant
         }
-        bool zero = false;
-        for (int i = 0; i < D; ++i)
-            if (s2[i] == 0) zero = true;
-        if (zero) continue;
-        cot_rec(g, o2, s2, grouped, out);
+        cot_rec(g, o2, s2, grouped, dst);
+    };
+    if (!grouped) {
+        for (int m = 0; m < nch; ++m) child(m, out);
+        return;
+    }
+    for (int grp = 0; grp <= D; ++grp) {
+        std::vector<std::vector<Leaf>> seqs;
+        size_t longest = 0;
+        for (int m = 0; m < nch; ++m) {
+            if (__builtin_popcount(m) != grp) continue;
+            seqs.emplace_back();
+            child(m, seqs.back());
+            longest = std::max(longest, seqs.back().size());
+        }
+        for (size_t i = 0; i < longest; ++i)
+            for (auto& q : seqs)
+                if (i < q.size()) out.push_back(q[i]);
     }
 }
 
