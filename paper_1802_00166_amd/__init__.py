@@ -17,6 +17,10 @@ LIB_PATH = os.path.join(_HERE, "libpcot.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError("libpcot.so is not built at %s; run __graft_entry__.build()" % LIB_PATH)
 
+# torch first: its HIP runtime then serves the library too (both carry the
+# soname libamdhip64.so.7), so device pointers and streams are shared.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # enums (include/pcot.h)
@@ -54,6 +58,10 @@ _SIGS = {
     "pcot_version": (ctypes.c_char_p, []),
     "pcot_dp_workspace": (_SZ, [_I64, _TP, _I32]),
     "pcot_dp_run": (_I32, [_P, _I64, _I64, _TP, _I32, _P, _P, _SZ, _P]),
+    "pcot_stencil_workspace_batched": (_SZ, [_I32, _I32, _I32, _I64P, _I64P, _TP, _I32]),
+    "pcot_stencil_run_batched": (_I32, [_I32, _I32, _I32, _I64P, _I64P, _TP, _I32, ctypes.POINTER(_P),
+                                        ctypes.POINTER(_P), _P, _SZ, _P]),
+    "pcot_error_norms": (_I32, [_I32, _I32, _I64P, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "pcot_kernel_timing": (_I32, [_I32]),
     "pcot_kernel_timing_read": (_I32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -143,6 +151,61 @@ def stencil_run(kind: str, dtype: str, x, T: int, tile=None, schedule: str = "na
                           stream_ptr(stream))
     check(st)
     return out
+
+
+def _batch_args(shapes, Ts, tiles):
+    n = len(shapes)
+    if not (len(Ts) == n and len(tiles) == n):
+        raise ValueError("shapes, Ts and tiles must have one entry per instance")
+    dims = (ctypes.c_int64 * (3 * n))()
+    for i, sh in enumerate(shapes):
+        for j, v in enumerate(sh):
+            dims[3 * i + j] = int(v)
+    tarr = (ctypes.c_int64 * n)(*[int(t) for t in Ts])
+    tl = (pcot_tile * n)(*[tp if isinstance(tp, pcot_tile) else make_tile(*tp) for tp in tiles])
+    return n, dims, tarr, tl
+
+
+def workspace_bytes_batched(kind: str, dtype: str, shapes, Ts, tiles, schedule: str) -> int:
+    n, dims, tarr, tl = _batch_args(shapes, Ts, tiles)
+    nb = pcot_stencil_workspace_batched(KINDS[kind], DTYPES[dtype], n, dims, tarr, tl, SCHEDULES[schedule])
+    if nb == 0:
+        raise PcotError(-1, last_error())
+    return int(nb)
+
+
+def stencil_run_batched(kind: str, dtype: str, xs, Ts, tiles, schedule: str = "slt_wave", outs=None,
+                        workspace=None, stream=None):
+    """Runs instance i for Ts[i] steps with tiles[i], all in one persistent launch.
+
+    xs: list of contiguous device tensors (extents incl. boundary).  Returns outs."""
+    torch = _torch()
+    shapes = [tuple(x.shape) for x in xs]
+    if outs is None:
+        outs = [torch.empty_like(x) for x in xs]
+    n, dims, tarr, tl = _batch_args(shapes, Ts, tiles)
+    nb = workspace_bytes_batched(kind, dtype, shapes, Ts, tl, schedule)
+    if workspace is None or workspace.numel() < nb:
+        workspace = alloc_workspace(nb, xs[0].device)
+    ins = (_P * n)(*[x.data_ptr() for x in xs])
+    ous = (_P * n)(*[y.data_ptr() for y in outs])
+    check(pcot_stencil_run_batched(KINDS[kind], DTYPES[dtype], n, dims, tarr, tl, SCHEDULES[schedule], ins, ous,
+                                   ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()),
+                                   stream_ptr(stream)))
+    return outs
+
+
+def error_norms(dtype: str, x, r, stream=None) -> dict:
+    """Binary64 device norms of x - r over the interior (r: float64 device tensor)."""
+    torch = _torch()
+    assert r.dtype == torch.float64 and r.shape == x.shape and r.is_contiguous() and x.is_contiguous()
+    out = (ctypes.c_double * 4)()
+    check(pcot_error_norms(DTYPES[dtype], x.dim(), _dims(x.shape), ctypes.c_void_p(x.data_ptr()),
+                           ctypes.c_void_p(r.data_ptr()), out, stream_ptr(stream)))
+    max_abs, max_ref, sse, ssr = list(out)
+    return {"max_abs": max_abs, "max_ref": max_ref, "sum_sq": sse, "sum_ref_sq": ssr,
+            "max_rel": max_abs / max_ref if max_ref > 0 else float("nan"),
+            "l2_rel": (sse / ssr) ** 0.5 if ssr > 0 else float("nan")}
 
 
 def stream_status(workspace, stream=None) -> int:

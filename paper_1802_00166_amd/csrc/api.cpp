@@ -4,6 +4,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <array>
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -16,12 +18,6 @@
 #include "plan.hpp"
 
 namespace pcot {
-bool tiled2d_supported(const int* b);
-hipError_t launch_tiled2d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
-bool tiled1d_supported(const int* b);
-hipError_t launch_tiled1d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
-bool tiled3d_supported(const int* b);
-hipError_t launch_tiled3d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
 struct DPLaunch {
     const long long* p;
     void* Cw;
@@ -396,6 +392,158 @@ pcot_status dp_validate(int64_t N, int64_t pmax, const pcot_tile* tile, int32_t 
     return PCOT_OK;
 }
 
+// ---------------------------------------------------------------- batches ---
+// A batch shares kind, dtype and schedule; the persistent launch needs one
+// kernel instance, so the tiles share the launch shape (b_x, and b_y for
+// Heat-3D, whose block is b_y waves) while b_t and the other sizes may
+// differ per instance.
+struct BatchPlan {
+    std::vector<QEntry> host;
+    std::vector<uint16_t> hprob;
+    std::vector<std::array<int64_t, 4>> cnt;
+    QEntry* dev = nullptr;
+    uint16_t* devp = nullptr;
+    ~BatchPlan() {
+        if (dev) (void)hipFree(dev);
+        if (devp) (void)hipFree(devp);
+    }
+};
+std::map<std::vector<int64_t>, std::unique_ptr<BatchPlan>> g_bplans;
+
+struct Batch {
+    std::vector<Prob> p;
+    int lb[4] = {1, 1, 1, 1};  // launch shape
+};
+
+pcot_status batch_validate(int32_t kind, int32_t dtype, int32_t n, const int64_t* dims, const int64_t* T,
+                           const pcot_tile* tiles, int32_t schedule, Batch& B) {
+    if (n < 1 || n > 65535) return fail(PCOT_ERR_INVALID, "batch of %d instances (need 1 .. 65535)", n);
+    if (!dims || !T || !tiles) return fail(PCOT_ERR_INVALID, "dims/T/tiles is NULL");
+    if (schedule == PCOT_NAIVE) return fail(PCOT_ERR_UNSUPPORTED, "batched runs need a tiled schedule");
+    B.p.resize(n);
+    for (int i = 0; i < n; ++i) {
+        pcot_status st = validate(kind, dtype, dims + 3 * (size_t)i, T[i], tiles + i, schedule, B.p[i]);
+        if (st != PCOT_OK) return fail(st, "instance %d: %s", i, g_err.c_str());
+        if (!tile_ok(kind, B.p[i].b)) return fail(PCOT_ERR_UNSUPPORTED, "instance %d: tile not runnable", i);
+    }
+    const Prob& p0 = B.p[0];
+    const int d = p0.d;
+    for (int j = 0; j < 4; ++j) B.lb[j] = p0.b[j];
+    for (int i = 1; i < n; ++i) {
+        const Prob& q = B.p[i];
+        if (q.b[d] != p0.b[d]) return fail(PCOT_ERR_UNSUPPORTED, "instance %d: b_x differs within the batch", i);
+        if (d == 3 && q.b[2] != p0.b[2]) return fail(PCOT_ERR_UNSUPPORTED, "instance %d: b_y differs within the batch", i);
+        for (int j = 0; j < d; ++j) B.lb[j] = std::max(B.lb[j], q.b[j]);
+    }
+    if (!tile_ok(kind, B.lb)) return fail(PCOT_ERR_UNSUPPORTED, "no executor instance covers the batch's largest tile");
+    return PCOT_OK;
+}
+
+struct BatchLayout {
+    size_t hdr = 0, probs = 0, counters = 0, ncounters = 0, total = 0;
+    std::vector<size_t> cnt_off, field_off;
+};
+
+BatchLayout batch_layout(const Batch& B) {
+    BatchLayout L;
+    const size_t n = B.p.size();
+    size_t off = align_up(HDR_WORDS * sizeof(unsigned));
+    L.probs = off;
+    off += align_up(n * sizeof(TiledProblem));
+    L.counters = off;
+    size_t c = 0;
+    for (const Prob& p : B.p) {
+        StencilGeom g = geom_of(p);
+        size_t nc = 1;
+        for (int i = 0; i <= p.d; ++i) nc *= (size_t)g.cnt[i];
+        L.cnt_off.push_back(c);
+        c += (nc + 63) / 64 * 64;
+    }
+    L.ncounters = c;
+    off += align_up(c * sizeof(unsigned));
+    for (const Prob& p : B.p) {
+        L.field_off.push_back(off);
+        off += align_up((size_t)p.elems * elem_bytes(p.dtype));
+    }
+    L.total = off;
+    return L;
+}
+
+// Leaves of all instances merged by fractional progress: leaf j of an
+// instance with m leaves gets key (j + 1/2) / m, so every instance advances
+// through its own order at the same relative pace and all finish near the end
+// of the queue; ties go to the instance with more updates.  Each instance's
+// own order is kept, so the merged queue stays topological.
+pcot_status get_batch_plan(const Batch& B, int sched, BatchPlan** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::vector<int64_t> key = {dev, B.p[0].d, sched, (int64_t)B.p.size()};
+    for (const Prob& p : B.p) {
+        key.insert(key.end(), {p.n[0], p.n[1], p.n[2], p.T, p.b[0], p.b[1], p.b[2], p.b[3]});
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_bplans.find(key);
+    if (it != g_bplans.end()) {
+        *out = it->second.get();
+        return PCOT_OK;
+    }
+    auto P = std::make_unique<BatchPlan>();
+    struct Item {
+        double key;
+        int64_t weight;
+        int inst;
+        QEntry e;
+    };
+    std::vector<Item> items;
+    for (size_t i = 0; i < B.p.size(); ++i) {
+        const Prob& p = B.p[i];
+        StencilGeom g = geom_of(p);
+        for (int j = 0; j <= p.d; ++j)
+            if (g.cnt[j] >= 65535) return fail(PCOT_ERR_UNSUPPORTED, "instance %zu: tile grid too large", i);
+        P->cnt.push_back({g.cnt[0], g.cnt[1], g.cnt[2], g.cnt[3]});
+        int64_t w = p.T;
+        for (int j = 0; j < p.d; ++j) w *= p.n[j] - 2;
+        std::vector<Leaf> leaves = enumerate_leaves(g, sched);
+        const double m = (double)leaves.size();
+        for (size_t j = 0; j < leaves.size(); ++j) {
+            Item it2;
+            it2.key = ((double)j + 0.5) / m;
+            it2.weight = w;
+            it2.inst = (int)i;
+            for (int q = 0; q < 4; ++q) it2.e.k[q] = (uint16_t)leaves[j].k[q];
+            items.push_back(it2);
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+        if (a.key != b.key) return a.key < b.key;
+        if (a.weight != b.weight) return a.weight > b.weight;
+        return a.inst < b.inst;
+    });
+    for (const Item& x : items) {
+        P->host.push_back(x.e);
+        P->hprob.push_back((uint16_t)x.inst);
+    }
+    if (!items.empty()) {
+        HIP_TRY(hipMalloc(&P->dev, sizeof(QEntry) * items.size()));
+        HIP_TRY(hipMemcpy(P->dev, P->host.data(), sizeof(QEntry) * items.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMalloc(&P->devp, sizeof(uint16_t) * items.size()));
+        HIP_TRY(hipMemcpy(P->devp, P->hprob.data(), sizeof(uint16_t) * items.size(), hipMemcpyHostToDevice));
+    }
+    *out = P.get();
+    g_bplans.emplace(key, std::move(P));
+    return PCOT_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+// Binary64 error norms: one scratch buffer per device, made on first use.
+std::mutex g_nmu;
+std::map<int, double*> g_norm_scratch;
+
 }  // namespace
 
 extern "C" {
@@ -507,6 +655,103 @@ pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, i
     if (st != PCOT_OK) return st;
     HIP_TRY(launch_tiled_kind(kind, dtype, p.b, L, 0, s));
     return timed_launch_end(s, stop);
+}
+
+size_t pcot_stencil_workspace_batched(int32_t kind, int32_t dtype, int32_t n, const int64_t* dims,
+                                      const int64_t* T, const pcot_tile* tiles, int32_t schedule) {
+    Batch B;
+    if (batch_validate(kind, dtype, n, dims, T, tiles, schedule, B) != PCOT_OK) return 0;
+    return batch_layout(B).total;
+}
+
+pcot_status pcot_stencil_run_batched(int32_t kind, int32_t dtype, int32_t n, const int64_t* dims,
+                                     const int64_t* T, const pcot_tile* tiles, int32_t schedule,
+                                     const void* const* in, void* const* out, void* workspace, size_t ws_bytes,
+                                     void* stream) {
+    Batch B;
+    pcot_status st = batch_validate(kind, dtype, n, dims, T, tiles, schedule, B);
+    if (st != PCOT_OK) return st;
+    if (!in || !out) return fail(PCOT_ERR_INVALID, "in/out is NULL");
+    const BatchLayout W = batch_layout(B);
+    if (!workspace || ws_bytes < W.total)
+        return fail(PCOT_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, W.total);
+    if (((uintptr_t)workspace) % ALIGN) return fail(PCOT_ERR_INVALID, "workspace not 256-byte aligned");
+    for (int i = 0; i < n; ++i) {
+        const size_t bytes = (size_t)B.p[i].elems * elem_bytes(dtype);
+        if (!in[i] || !out[i]) return fail(PCOT_ERR_INVALID, "instance %d: in/out is NULL", i);
+        if (overlaps(in[i], bytes, out[i], bytes)) return fail(PCOT_ERR_INVALID, "instance %d: in and out overlap", i);
+        if (overlaps(out[i], bytes, workspace, W.total) || overlaps(in[i], bytes, workspace, W.total))
+            return fail(PCOT_ERR_INVALID, "instance %d: in/out overlaps the workspace", i);
+    }
+    BatchPlan* plan = nullptr;
+    st = get_batch_plan(B, schedule, &plan);
+    if (st != PCOT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    unsigned* hdr = (unsigned*)(ws + W.hdr);
+    unsigned* counters = (unsigned*)(ws + W.counters);
+    TiledProblem* probs = (TiledProblem*)(ws + W.probs);
+    std::vector<TiledProblem> hp(n);
+    for (int i = 0; i < n; ++i) {
+        const Prob& p = B.p[i];
+        TiledProblem& P = hp[i];
+        memset(&P, 0, sizeof P);
+        P.in = in[i];
+        void* field = ws + W.field_off[i];
+        if (p.T & 1) { P.buf1 = out[i]; P.buf0 = field; }
+        else { P.buf0 = out[i]; P.buf1 = field; }
+        for (int j = 0; j < 3; ++j) P.n[j] = (int)p.n[j];
+        P.T = (int)p.T;
+        for (int j = 0; j < 4; ++j) {
+            P.b[j] = p.b[j];
+            P.cnt[j] = (int)plan->cnt[i][j];
+        }
+        P.counters = counters + W.cnt_off[i];
+    }
+    HIP_TRY(launch_fill_u32(hdr, HDR_WORDS, 0u, s));
+    HIP_TRY(launch_fill_u32(counters, W.ncounters, 0u, s));
+    HIP_TRY(launch_put_problems(probs, hp.data(), n, s));
+    HIP_TRY(launch_copy_boundary_batched(dtype, probs, n, B.p[0].d, s));
+    for (int i = 0; i < n; ++i)
+        if (B.p[i].T == 0)
+            HIP_TRY(hipMemcpyAsync(out[i], in[i], (size_t)B.p[i].elems * elem_bytes(dtype), hipMemcpyDeviceToDevice, s));
+    if (plan->host.empty()) return PCOT_OK;
+    TiledLaunch L;
+    memset(&L, 0, sizeof L);
+    L.probs = probs;
+    L.queue = plan->dev;
+    L.qprob = plan->devp;
+    L.nq = (int)plan->host.size();
+    L.hdr = hdr;
+    L.limit_ticks = watchdog_ticks();
+    hipEvent_t stop;
+    st = timed_launch_begin(s, &stop);
+    if (st != PCOT_OK) return st;
+    HIP_TRY(launch_tiled_kind(kind, dtype, B.lb, L, 0, s));
+    return timed_launch_end(s, stop);
+}
+
+pcot_status pcot_error_norms(int32_t dtype, int32_t d, const int64_t* dims, const void* x, const double* r,
+                             double* out, void* stream) {
+    if (dtype < PCOT_F64 || dtype > PCOT_BF16) return fail(PCOT_ERR_INVALID, "unknown dtype %d", dtype);
+    if (d < 1 || d > 3) return fail(PCOT_ERR_INVALID, "d=%d (need 1..3)", d);
+    if (!dims || !x || !r || !out) return fail(PCOT_ERR_INVALID, "NULL argument");
+    int64_t n[3] = {1, 1, 1};
+    for (int i = 0; i < d; ++i) {
+        if (dims[i] < 3 || dims[i] > (1LL << 30)) return fail(PCOT_ERR_INVALID, "dims[%d]=%lld", i, (long long)dims[i]);
+        n[i] = dims[i];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_nmu);
+    double*& scratch = g_norm_scratch[dev];
+    if (!scratch) HIP_TRY(hipMalloc(&scratch, norms_scratch_bytes()));
+    HIP_TRY(launch_norms(dtype, d, n, x, r, scratch, s));
+    const size_t res = norms_scratch_bytes() / sizeof(double) - 4;
+    HIP_TRY(hipMemcpyAsync(out, scratch + res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PCOT_OK;
 }
 
 size_t pcot_dp_workspace(int64_t N, const pcot_tile* tile, int32_t schedule) {

@@ -115,4 +115,117 @@ __device__ __forceinline__ void signal(unsigned* cnt) {
     __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Does tile k (k[0] time, k[1..D] spatial, outer to inner) of problem P hold
+// a point of the skewed domain 0 <= t < T, 1 + t <= j_d <= n_d - 2 + t ?
+template <int D>
+__device__ __forceinline__ bool tile_nonempty(const TiledProblem& P, const int* k) {
+#pragma unroll
+    for (int i = 0; i <= D; ++i)
+        if (k[i] < 0 || k[i] >= P.cnt[i]) return false;
+    const int tlo = k[0] * P.b[0];
+    int tmin = tlo, tmax = min(tlo + P.b[0] - 1, P.T - 1);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const int lo = 1 + k[i + 1] * P.b[i + 1];
+        tmin = max(tmin, lo - P.n[i] + 2);
+        tmax = min(tmax, lo + P.b[i + 1] - 2);
+    }
+    return tmin <= tmax;
+}
+
+// Does every level of tile k keep all its points inside the interior?
+template <int D>
+__device__ __forceinline__ bool tile_interior(const TiledProblem& P, const int* k) {
+    const int t0 = k[0] * P.b[0];
+    const int t1 = t0 + min(P.b[0], P.T - t0) - 1;
+    bool in = true;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const int lo = 1 + k[i + 1] * P.b[i + 1];
+        in = in && (lo - t1 >= 1) && (lo + P.b[i + 1] - 1 - t0 <= P.n[i] - 2);
+    }
+    return in;
+}
+
+__device__ __forceinline__ size_t tile_index(const TiledProblem& P, const int* k, int D) {
+    size_t idx = 0;
+    for (int i = 0; i <= D; ++i) idx = idx * P.cnt[i] + k[i];
+    return idx;
+}
+
+// One tile of the device queue, run by the calling block:
+//  1. take a ticket (the tile is the ticket, not blockIdx: tickets are taken
+//     in the order blocks start, so every predecessor of a ticket belongs to
+//     a block that is already running and the waits below always end);
+//  2. wave 0 waits until every non-empty predecessor (offsets in {0,-1}^(D+1))
+//     has signalled, bounded by the watchdog;
+//  3. acquire (each wave), run `exec(P, k)`, release (each wave: the barrier
+//     does not wait for outstanding stores), then one thread signals every
+//     successor.
+// Control values live in SGPRs (uni): with per-lane copies the compiler
+// builds per-lane loops around the thread-0 regions that never terminate.
+template <int D, typename Exec>
+__device__ __forceinline__ void run_queued_tile(const TiledLaunch& Lc, int* s_tk, int* s_go, Exec&& exec) {
+    const int wave = uni((int)(threadIdx.x >> 6));
+    if (threadIdx.x == 0)
+        *s_tk = (int)__hip_atomic_fetch_add(Lc.hdr + HDR_TICKET, 1u, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int tk = uni(*s_tk);
+    if (tk >= Lc.nq) return;
+    const QEntry e = Lc.queue[tk];
+    const int pi = Lc.qprob ? uni((int)Lc.qprob[tk]) : 0;
+    const TiledProblem P = Lc.probs[pi];
+    int k[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) k[i] = uni((int)e.k[i]);
+    unsigned* cnt = P.counters + tile_index(P, k, D);
+    if (wave == 0) {
+        unsigned need = 0;
+#pragma unroll
+        for (int m = 1; m < (1 << (D + 1)); ++m) {
+            int q[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int i = 0; i <= D; ++i) q[i] = k[i] - ((m >> (D - i)) & 1);
+            need += tile_nonempty<D>(P, q);
+        }
+        const bool go = wait_ready(cnt, need, Lc.hdr, Lc.limit_ticks);
+        if (threadIdx.x == 0) *s_go = go ? 1 : 0;
+    }
+    __syncthreads();
+    const int go = uni(*s_go);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (go) exec(P, k);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int m = 1; m < (1 << (D + 1)); ++m) {
+            int q[4] = {0, 0, 0, 0};
+            bool in = true;
+#pragma unroll
+            for (int i = 0; i <= D; ++i) {
+                q[i] = k[i] + ((m >> (D - i)) & 1);
+                in = in && q[i] < P.cnt[i];
+            }
+            if (in) signal(P.counters + tile_index(P, q, D));
+        }
+    }
+}
+
+// Pointer known to be the same in every lane, moved into SGPRs.
+__device__ __forceinline__ const void* uptr(const void* p) {
+    const uintptr_t v = (uintptr_t)p;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return (const void*)(((uintptr_t)hi << 32) | lo);
+}
+
+// a if sel_b is even, b if odd, by bit masks (a conditional pick between
+// two struct fields would be lowered to an indexed load from a stack copy).
+__device__ __forceinline__ uintptr_t pick(uintptr_t a, uintptr_t b, int sel_b) {
+    const uintptr_t m = (uintptr_t)0 - (uintptr_t)(sel_b & 1);
+    return (a & ~m) | (b & m);
+}
+
 }  // namespace pcot

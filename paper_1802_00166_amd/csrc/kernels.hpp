@@ -51,12 +51,23 @@ struct TiledLaunch {
 // Writes one problem descriptor to device memory (a kernel, so that it can be
 // recorded into a HIP graph).
 hipError_t launch_put_problem(TiledProblem* dst, const TiledProblem& v, hipStream_t s);
+hipError_t launch_put_problems(TiledProblem* dst, const TiledProblem* v, int n, hipStream_t s);
+// Boundary of every problem's u_0 into both of its buffers (one launch).
+hipError_t launch_copy_boundary_batched(int dtype, const TiledProblem* probs, int nprob, int d, hipStream_t s);
 
-// Is the tile shape runnable by a tiled executor for (kind, dtype)?
-bool tiled_supported(int kind, int dtype, const int* b);
-// Launches the persistent tiled executor on `stream`.  `grid_cap` bounds the
-// number of blocks (0: fill the device).
-hipError_t launch_tiled(int kind, int dtype, const int* b, const TiledLaunch& L, int grid_cap,
+// Error norms (binary64): `scratch` holds norms_scratch_bytes(); the four
+// results land at the end of it.
+size_t norms_scratch_bytes();
+hipError_t launch_norms(int dtype, int d, const int64_t* n, const void* x, const double* r, double* scratch,
                         hipStream_t s);
+
+// Tiled executors, one per stencil kind.  b = {b_t, spatial sizes outer..inner}.
+// *_supported: is the tile shape runnable; launch_*: one block per queue entry.
+bool tiled1d_supported(const int* b);
+hipError_t launch_tiled1d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
+bool tiled2d_supported(const int* b);
+hipError_t launch_tiled2d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
+bool tiled3d_supported(const int* b);
+hipError_t launch_tiled3d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
 
 }  // namespace pcot

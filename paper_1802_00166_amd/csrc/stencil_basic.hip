@@ -32,12 +32,34 @@ hipError_t launch_put_problem(TiledProblem* dst, const TiledProblem& v, hipStrea
     return hipGetLastError();
 }
 
+// Up to PUT_CHUNK descriptors per launch, passed by value (kernel arguments
+// are recorded by value into a HIP graph, unlike a pageable host copy).
+constexpr int PUT_CHUNK = 32;
+struct ProblemChunk {
+    TiledProblem p[PUT_CHUNK];
+};
+__global__ void k_put_problems(TiledProblem* dst, ProblemChunk c, int n) {
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = c.p[threadIdx.x];
+}
+
+hipError_t launch_put_problems(TiledProblem* dst, const TiledProblem* v, int n, hipStream_t s) {
+    for (int i = 0; i < n; i += PUT_CHUNK) {
+        ProblemChunk c;
+        const int m = n - i < PUT_CHUNK ? n - i : PUT_CHUNK;
+        for (int j = 0; j < m; ++j) c.p[j] = v[i + j];
+        hipLaunchKernelGGL(k_put_problems, dim3(1), dim3(64), 0, s, dst + i, c, m);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // ------------------------------------------------------- boundary copy ---
 // Copies the outer face of a d-dimensional field (2d segments: each axis at
 // index 0 and n-1; edges are copied more than once, with the same value).
 template <typename S>
-__global__ void k_copy_boundary(const S* __restrict__ src, S* __restrict__ dst0, S* __restrict__ dst1,
-                                int d, long long n0, long long n1, long long n2) {
+__device__ void copy_boundary_range(const S* __restrict__ src, S* __restrict__ dst0, S* __restrict__ dst1, int d,
+                                    long long n0, long long n1, long long n2, long long start, long long stride) {
     const long long n[3] = {n0, n1, n2};
     long long seg_len[3];
     for (int a = 0; a < d; ++a) {
@@ -48,8 +70,7 @@ __global__ void k_copy_boundary(const S* __restrict__ src, S* __restrict__ dst0,
     }
     long long total = 0;
     for (int a = 0; a < d; ++a) total += 2 * seg_len[a];
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    for (long long i = start; i < total; i += stride) {
         long long r = i;
         int a = 0;
         while (r >= 2 * seg_len[a]) { r -= 2 * seg_len[a]; ++a; }
@@ -67,6 +88,33 @@ __global__ void k_copy_boundary(const S* __restrict__ src, S* __restrict__ dst0,
         dst0[off] = v;
         if (dst1) dst1[off] = v;
     }
+}
+
+template <typename S>
+__global__ void k_copy_boundary(const S* __restrict__ src, S* __restrict__ dst0, S* __restrict__ dst1,
+                                int d, long long n0, long long n1, long long n2) {
+    copy_boundary_range(src, dst0, dst1, d, n0, n1, n2, (long long)blockIdx.x * blockDim.x + threadIdx.x,
+                        (long long)gridDim.x * blockDim.x);
+}
+
+// Batched form: blockIdx.y selects the problem; u_0's boundary goes to both
+// of its buffers.
+template <typename S>
+__global__ void k_copy_boundary_batched(const TiledProblem* __restrict__ probs, int d) {
+    const TiledProblem& P = probs[blockIdx.y];
+    copy_boundary_range((const S*)P.in, (S*)P.buf0, (S*)P.buf1, d, P.n[0], P.n[1], P.n[2],
+                        (long long)blockIdx.x * blockDim.x + threadIdx.x, (long long)gridDim.x * blockDim.x);
+}
+
+hipError_t launch_copy_boundary_batched(int dtype, const TiledProblem* probs, int nprob, int d, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    const dim3 grid(64, (unsigned)nprob);
+    switch (dtype) {
+        case 0: hipLaunchKernelGGL(k_copy_boundary_batched<double>, grid, dim3(256), 0, s, probs, d); break;
+        case 1: hipLaunchKernelGGL(k_copy_boundary_batched<float>, grid, dim3(256), 0, s, probs, d); break;
+        default: hipLaunchKernelGGL(k_copy_boundary_batched<uint16_t>, grid, dim3(256), 0, s, probs, d); break;
+    }
+    return hipGetLastError();
 }
 
 template <typename S>

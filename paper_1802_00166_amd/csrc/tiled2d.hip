@@ -42,25 +42,6 @@ namespace {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__device__ __forceinline__ bool leaf_nonempty(const TiledProblem& P, int kt, int ky, int kx) {
-    if (kt < 0 || ky < 0 || kx < 0 || kt >= P.cnt[0] || ky >= P.cnt[1] || kx >= P.cnt[2]) return false;
-    const int tlo = kt * P.b[0];
-    int tmin = tlo, tmax = min(tlo + P.b[0] - 1, P.T - 1);
-    const int ylo = 1 + ky * P.b[1], xlo = 1 + kx * P.b[2];
-    tmin = max(tmin, max(ylo - P.n[0] + 2, xlo - P.n[1] + 2));
-    tmax = min(tmax, min(ylo + P.b[1] - 2, xlo + P.b[2] - 2));
-    return tmin <= tmax;
-}
-
-__device__ __forceinline__ bool leaf_interior(const TiledProblem& P, int kt, int ky, int kx) {
-    const int t0 = kt * P.b[0];
-    const int nt = min(P.b[0], P.T - t0);
-    const int t1 = t0 + nt - 1;
-    const int jy0 = 1 + ky * P.b[1], jx0 = 1 + kx * P.b[2];
-    return (jy0 - t1 >= 1) && (jy0 + P.b[1] - 1 - t0 <= P.n[0] - 2) && (jx0 - t1 >= 1) &&
-           (jx0 + P.b[2] - 1 - t0 <= P.n[1] - 2);
-}
-
 template <int C, int G> struct Cfg {
     static constexpr int ROW = 64 * C + 2;          // staged row: 2 left-face values + 64*C columns
     static constexpr int KB = G == 1 ? 4 : 8;       // bottom-plane rows per staging chunk
@@ -75,20 +56,6 @@ template <typename A, int C, int G> struct Smem {
     A junk[G][128];                    // sink for the lanes that stage nothing
     int tk, go;
 };
-
-__device__ __forceinline__ uintptr_t pick(uintptr_t a, uintptr_t b, int sel_b) {
-    const uintptr_t m = (uintptr_t)0 - (uintptr_t)(sel_b & 1);
-    return (a & ~m) | (b & m);
-}
-
-__device__ __forceinline__ const void* uptr(const void* p) {
-    // a wave-uniform pointer moved into SGPRs; the value must already be the
-    // same in every lane (readfirstlane takes the first active lane's value)
-    const uintptr_t v = (uintptr_t)p;
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
-    return (const void*)(((uintptr_t)hi << 32) | lo);
-}
 
 template <typename S, int C, int L, int G, bool BND>
 __device__ __forceinline__ void exec_tile(const TiledProblem& P, int kt, int ky, int kx,
@@ -550,59 +517,18 @@ template <typename S, int C, int L, int G>
 __global__ void __launch_bounds__(64 * G) k_tiled2d(TiledLaunch Lc) {
     using A = typename Tr<S>::A;
     __shared__ Smem<A, C, G> sm;
-    // One block per queue entry.  The tile is the block's ticket, not its
-    // blockIdx: tickets are handed out in the order blocks start, so every
-    // predecessor of a ticket was taken earlier by a block that is running,
-    // and the waits below always end.  (A persistent loop around the
-    // thread-0 regions below is lowered into per-lane loops that deadlock.)
-    const int wave = uni((int)(threadIdx.x >> 6));
-    if (threadIdx.x == 0)
-        sm.tk = (int)__hip_atomic_fetch_add(Lc.hdr + HDR_TICKET, 1u, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int tk = uni(sm.tk);
-    if (tk >= Lc.nq) return;
-    const QEntry e = Lc.queue[tk];
-    const int pi = Lc.qprob ? uni((int)Lc.qprob[tk]) : 0;
-    const TiledProblem P = Lc.probs[pi];
-    const int kt = uni((int)e.k[0]), ky = uni((int)e.k[1]), kx = uni((int)e.k[2]);
-    unsigned* cnt = P.counters + ((size_t)kt * P.cnt[1] + ky) * P.cnt[2] + kx;
-    if (wave == 0) {
-        unsigned need = 0;
-#pragma unroll
-        for (int m = 1; m < 8; ++m)
-            need += leaf_nonempty(P, kt - ((m >> 2) & 1), ky - ((m >> 1) & 1), kx - (m & 1));
-        const bool go = wait_ready(cnt, need, Lc.hdr, Lc.limit_ticks);
-        if (threadIdx.x == 0) sm.go = go ? 1 : 0;
-    }
-    __syncthreads();
-    const int go = uni(sm.go);
-    // every wave acquires: the barrier alone does not order its loads after
-    // another wave's cache invalidation
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (go) {
+    run_queued_tile<2>(Lc, &sm.tk, &sm.go, [&](const TiledProblem& P, const int* k) {
+        const int kt = k[0], ky = k[1], kx = k[2];
         const bool full = (kt + 1) * P.b[0] <= P.T && P.b[0] == G * L;
         if (full) {
-            if (leaf_interior(P, kt, ky, kx))
+            if (tile_interior<2>(P, k))
                 exec_full<S, C, L, G, false>(P, kt, ky, kx, sm);
             else
                 exec_full<S, C, L, G, true>(P, kt, ky, kx, sm);
         } else {
             exec_tile<S, C, L, G, true>(P, kt, ky, kx, sm);
         }
-    }
-    // every wave releases its own stores (the barrier does not wait for
-    // outstanding vector-memory stores), then one thread signals
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int m = 1; m < 8; ++m) {
-            const int a = (m >> 2) & 1, b = (m >> 1) & 1, c = m & 1;
-            if (kt + a < P.cnt[0] && ky + b < P.cnt[1] && kx + c < P.cnt[2])
-                signal(cnt + ((size_t)a * P.cnt[1] + b) * P.cnt[2] + c);
-        }
-    }
+    });
 }
 
 template <typename S, int C, int L, int G>

@@ -1,0 +1,221 @@
+// Time-skewed tile executor for the 7-point Heat-3D stencil.
+//
+// A leaf is t in [t0, t0+nt) x jz x jy x jx (skewed j = i + t, sizes bz, by,
+// bx = 64).  Level t at (jz, jy, jx) updates u_{t+1} at (jz-t, jy-t, jx-t)
+// from level t-1 outputs at
+//   u  (jz-1, jy-1, jx-1),  x+ (jz-1, jy-1, jx),  x- (jz-1, jy-1, jx-2),
+//   y+ (jz-1, jy,   jx-1),  y- (jz-1, jy-2, jx-1),
+//   z+ (jz,   jy-1, jx-1),  z- (jz-2, jy-1, jx-1).
+//
+// Mapping: the block has by waves; thread (w, lane) owns column (jy0+w,
+// jx0+lane).  Levels are pipelined along jz: at step s, level l handles plane
+// jz0 + s - l, so the levels of one step are independent and one barrier per
+// step suffices.  Each level's output planes (with a two-wide halo in y and x
+// holding the neighbour tiles' values, prefetched one step ahead) sit in a
+// 4-slot LDS ring: plane jz being written, jz-1..jz-3 readable.  Ring 0 holds
+// the tile's input u_t0, streamed in plane by plane.  The planes below the
+// tile (z-face) come from the z-neighbour tile at tile start.  Stores: the
+// top level at every point, and the two-wide high faces in x, y and z of every
+// other level.  Points outside the interior are carried unchanged.
+#include "bufio.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pcot {
+
+namespace {
+
+template <typename S>
+__device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, typename Tr<S>::A* lds) {
+    using A = typename Tr<S>::A;
+    constexpr int ES = sizeof(S);
+    constexpr int BX = 64, RX = BX + 2;
+    const int lane = threadIdx.x & 63;
+    const int w = uni((int)(threadIdx.x >> 6));
+    const int nthr = blockDim.x;
+    const int nz = P.n[0], ny = P.n[1], nx = P.n[2];
+    const int bt = P.b[0], bz = P.b[1], by = P.b[2];
+    const int RY = by + 2, PL = RY * RX;  // plane of the ring, with halo
+    const int t0 = k[0] * bt;
+    const int nt = min(bt, P.T - t0);
+    const int ttop = t0 + nt - 1;
+    const int jz0 = 1 + k[1] * bz, jy0 = 1 + k[2] * by, jx0 = 1 + k[3] * BX;
+    const uint32_t bytes = (uint32_t)nz * (uint32_t)ny * (uint32_t)nx * ES;
+    const uintptr_t pin = (uintptr_t)uptr(P.in), pb0 = (uintptr_t)uptr(P.buf0), pb1 = (uintptr_t)uptr(P.buf1);
+    auto src_of = [&](int t) {  // holds u_t
+        return make_rsrc(uptr((const void*)pick(pick(pb0, pb1, t), pin, t == 0)), bytes);
+    };
+    auto inside = [&](int z, int y, int x) {
+        return z >= 1 && z <= nz - 2 && y >= 1 && y <= ny - 2 && x >= 1 && x <= nx - 2;
+    };
+    auto offs = [&](int z, int y, int x) { return ((z * ny + y) * nx + x) * ES; };
+    // ring v (v = 0: u_t0; v = l+1: outputs of level t0+l), plane jz, ring row/col
+    auto ring = [&](int v, int jz, int ry, int rx) -> A& {
+        return lds[((v * 4 + ((jz - jz0 + 4) & 3)) * RY + ry) * RX + rx];
+    };
+    // ring v's value at skewed (jz, jy, jx): u_{t0+v} at the point
+    // (jz, jy, jx) - (t0+v-1), read from global; v must be wave-uniform
+    auto ldlvl = [&](int v, int jz, int jy, int jx) -> A {
+        const int t = t0 + v;  // buffer u_t
+        const int d = t - 1;
+        const int z = jz - d, y = jy - d, x = jx - d;
+        if (z < 0 || z >= nz || y < 0 || y >= ny) return A(0);
+        return IO<S>::ld(src_of(t), offs(z, y, x));
+    };
+
+    // ---- tile start: planes jz0-2, jz0-1 of every ring, and plane jz0 of ring 0
+    for (int v = 0; v <= nt; ++v) {
+        const int np = v == 0 ? 3 : 2;
+        for (int e = threadIdx.x; e < np * PL; e += nthr) {
+            const int pz = e / PL, rem = e % PL;
+            const int ry = rem / RX, rx = rem % RX;
+            const int jz = jz0 - 2 + pz;
+            ring(v, jz, ry, rx) = ldlvl(v, jz, jy0 - 2 + ry, jx0 - 2 + rx);
+        }
+    }
+    // prefetch registers: ring-0 plane and the halos of each level's next plane
+    constexpr int PF = 4;  // per-thread slots for one ring-0 plane: 4*256 >= 6*66 at by = 4
+    A p0[PF];
+    auto pf0_load = [&](int jz) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int e = threadIdx.x + i * nthr;
+            if (e < PL) p0[i] = ldlvl(0, jz, jy0 - 2 + e / RX, jx0 - 2 + e % RX);
+        }
+    };
+    auto pf0_store = [&](int jz) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int e = threadIdx.x + i * nthr;
+            if (e < PL) ring(0, jz, e / RX, e % RX) = p0[i];
+        }
+    };
+    // halo of plane jz of ring v (v >= 1): rows ry = 0, 1 (all RX columns) and
+    // columns rx = 0, 1 of rows 2..RY-1: 2*RX + 2*by values
+    const int HL = 2 * RX + 2 * by;
+    auto halo_pos = [&](int e, int& ry, int& rx) {
+        if (e < 2 * RX) { ry = e / RX; rx = e % RX; }
+        else { const int q = e - 2 * RX; ry = 2 + q / 2; rx = q & 1; }
+    };
+    constexpr int HPF = 8;  // per-thread halo slots per step (all levels)
+    A hv[HPF];
+    // The lanes of one wave may fetch halos of different levels, whose
+    // buffers differ with the parity of t: a buffer descriptor must be
+    // wave-uniform, so these loads take per-lane global addresses instead.
+    const long long nel = (long long)nz * ny * nx;
+    auto ldlvl_lane = [&](int v, int jz, int jy, int jx) -> A {
+        const int t = t0 + v, d = t - 1;  // v >= 1: t >= 1, never the input
+        const int z = jz - d, y = jy - d, x = jx - d;
+        const long long idx = ((long long)z * ny + y) * nx + x;
+        const bool ok = z >= 0 && z < nz && y >= 0 && y < ny && idx >= 0 && idx < nel;
+        const S* base = (const S*)pick(pb0, pb1, t);
+        return ok ? Tr<S>::ld(base + idx) : A(0);
+    };
+    auto halo_load = [&](int s) {  // halos of the planes the levels write at step s
+#pragma unroll
+        for (int i = 0; i < HPF; ++i) {
+            const int e = threadIdx.x + i * nthr;
+            const int l = e / HL, q = e % HL;
+            const int jz = jz0 + s - l;
+            if (l < nt && jz >= jz0 && jz < jz0 + bz) {
+                int ry, rx;
+                halo_pos(q, ry, rx);
+                hv[i] = ldlvl_lane(l + 1, jz, jy0 - 2 + ry, jx0 - 2 + rx);
+            }
+        }
+    };
+    auto halo_store = [&](int s) {
+#pragma unroll
+        for (int i = 0; i < HPF; ++i) {
+            const int e = threadIdx.x + i * nthr;
+            const int l = e / HL, q = e % HL;
+            const int jz = jz0 + s - l;
+            if (l < nt && jz >= jz0 && jz < jz0 + bz) {
+                int ry, rx;
+                halo_pos(q, ry, rx);
+                ring(l + 1, jz, ry, rx) = hv[i];
+            }
+        }
+    };
+    pf0_load(jz0 + 1);
+    halo_load(0);
+    __syncthreads();
+
+    const int jy = jy0 + w, jx = jx0 + lane;
+    const int ry = w + 2, rx = lane + 2;
+    const int nsteps = bz + nt - 1;
+    for (int s = 0; s < nsteps; ++s) {
+        // publish the prefetched ring-0 plane jz0+s+1 and the halos of this
+        // step's output planes, then start the next prefetches
+        pf0_store(jz0 + s + 1);
+        halo_store(s);
+        __syncthreads();
+        pf0_load(jz0 + s + 2);
+        halo_load(s + 1);
+        for (int l = 0; l < nt; ++l) {
+            const int jz = jz0 + s - l;
+            if (jz < jz0 || jz >= jz0 + bz) continue;  // uniform
+            const int t = t0 + l;
+            const A u = ring(l, jz - 1, ry - 1, rx - 1);
+            const A v = Tr<S>::rnd(heat3(u, ring(l, jz - 1, ry - 1, rx), ring(l, jz - 1, ry - 1, rx - 2),
+                                         ring(l, jz - 1, ry, rx - 1), ring(l, jz - 1, ry - 2, rx - 1),
+                                         ring(l, jz, ry - 1, rx - 1), ring(l, jz - 2, ry - 1, rx - 1)));
+            const int z = jz - t, y = jy - t, x = jx - t;
+            const bool in = inside(z, y, x);
+            const A out = in ? v : u;
+            ring(l + 1, jz, ry, rx) = out;
+            const bool face = t == ttop || lane >= BX - 2 || w >= by - 2 || jz >= jz0 + bz - 2;
+            if (face && in) IO<S>::st(src_of(t + 1), offs(z, y, x), out);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(512) k_tiled3d(TiledLaunch Lc) {
+    extern __shared__ char smem_raw[];
+    using A = typename Tr<S>::A;
+    __shared__ int s_tk, s_go;
+    run_queued_tile<3>(Lc, &s_tk, &s_go, [&](const TiledProblem& P, const int* k) {
+        exec3d<S>(P, k, reinterpret_cast<A*>(smem_raw));
+    });
+}
+
+template <typename S>
+hipError_t launch_dtype(const int* b, const TiledLaunch& Lc, hipStream_t s) {
+    if (Lc.nq <= 0) return hipSuccess;
+    using A = typename Tr<S>::A;
+    const int bt = b[0], by = b[2];
+    const size_t lds = (size_t)(bt + 1) * 4 * (by + 2) * 66 * sizeof(A);
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_tiled3d<S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_tiled3d<S>), dim3(Lc.nq), dim3(64 * by), lds, s, Lc);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool tiled3d_supported(const int* b) {
+    // b = {bt, bz, by, bx}; LDS rings must fit (sized for the f64 case)
+    if (b[3] != 64) return false;
+    if (b[2] != 2 && b[2] != 4 && b[2] != 8) return false;
+    if (b[1] < 2 || b[0] < 1 || b[0] > 16) return false;
+    // halo prefetch slots: HPF * threads >= bt * (2*66 + 2*by)
+    if (8 * 64 * b[2] < b[0] * (2 * 66 + 2 * b[2])) return false;
+    // ring-0 plane prefetch: 4 * threads >= (by+2) * 66
+    if (4 * 64 * b[2] < (b[2] + 2) * 66) return false;
+    const size_t lds = (size_t)(b[0] + 1) * 4 * (b[2] + 2) * 66 * 8;
+    return lds <= 150 * 1024;
+}
+
+hipError_t launch_tiled3d(int dtype, const int* b, const TiledLaunch& Lc, int, hipStream_t s) {
+    switch (dtype) {
+        case 0: return launch_dtype<double>(b, Lc, s);
+        case 1: return launch_dtype<float>(b, Lc, s);
+        default: return launch_dtype<uint16_t>(b, Lc, s);
+    }
+}
+
+}  // namespace pcot
