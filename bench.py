@@ -31,7 +31,7 @@ NY = NX = 4096
 T = 512
 UPDATES = (NY - 2) * (NX - 2) * T
 DEFAULT_TILE = (16, 64, 256)
-DEFAULT_SCHED = "cot_par"
+DEFAULT_SCHED = "slt_wave"
 
 HBM_PEAK_GBS = 8000.0
 # FP64 vector: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 non-fused FP64 ops/s
@@ -48,7 +48,7 @@ def alg_bytes_per_update(tile, elem=8):
     return elem * (2.0 / bt + 4.0 / bx + 4.0 / by)
 
 
-def roofline(tile, kernel_s):
+def roofline(tile, kernel_s, traffic=None):
     B = alg_bytes_per_update(tile)
     rate = UPDATES / kernel_s
     hbm_roof = HBM_PEAK_GBS * 1e9 / B
@@ -56,18 +56,57 @@ def roofline(tile, kernel_s):
     if hbm_roof <= alu_roof:
         ach = UPDATES * B / kernel_s / 1e9
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_update": round(B, 4), "updates_per_s_roof": hbm_roof}
     ach = OPS_PER_UPDATE * UPDATES / kernel_s / 1e12
     peak = FP64_OPS_PEAK / 1e12
     return {"bound": "alu", "achieved": round(ach, 3), "peak": round(peak, 2), "unit": "TFLOP/s",
-            "frac": round(ach / peak, 4), "traffic": None,
+            "frac": round(ach / peak, 4), "traffic": traffic,
             "alg_bytes_per_update": round(B, 4), "updates_per_s_roof": alu_roof}
 
 
-def cpu_baseline(u0, sample_T=16):
-    """Oracle on the host: the full 4096^2 field for `sample_T` steps, all host
-    threads (the threaded oracle gives the single-thread oracle's bits)."""
+def kernel_sources_digest():
+    """Digest of the sources of the Jacobi-2D executor; stored HBM-traffic
+    counters are reported only while it matches (else traffic is null)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("tiled2d.hip", "common.hpp", "bufio.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1802_00166_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(tile, sched):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, when
+    it was taken on this tile, schedule and kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic_jacobi2d_4096_T512_f64.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("digest") != kernel_sources_digest() or list(d.get("tile", [])) != list(tile) \
+            or d.get("schedule") != sched:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def calibrate_copy(reps=5):
+    """A plain device copy of known size (512 MiB read + 512 MiB written), for
+    scaling FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = 64 << 20
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": reps}), flush=True)
+
+
+def cpu_baseline(u0, sample_T=T):
+    """Oracle on the host: the full 4096^2 field for `sample_T` steps (by
+    default the whole job), on up to 16 host threads (the threaded oracle
+    gives the single-thread oracle's bits)."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
     oracle.stencil("jacobi2d", "f64", u0[:64, :64], 1, threads=threads)  # load/build
@@ -127,7 +166,12 @@ def main():
     ap.add_argument("--schedule", type=str, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-swept", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the plain copy used to scale the HBM traffic counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
               "(multi-GPU sharding is described in DESIGN.md, not built)" % args.gpus, file=sys.stderr)
@@ -180,7 +224,7 @@ def main():
         "data": "synthetic: sin(pi x)sin(pi y) + 1e-3*(2U-1) noise (SplitMix64 stream 2), zero boundary",
         "config": {"workload": "jacobi2d_5pt_4096x4096_T512_f64", "updates_per_step": UPDATES,
                    "tile_bt_by_bx": list(tile), "schedule": sched},
-        "roofline": dict(roofline(tile, kern_ms / 1e3), kernel_ms=round(kern_ms, 4)),
+        "roofline": dict(roofline(tile, kern_ms / 1e3, stored_traffic(tile, sched)), kernel_ms=round(kern_ms, 4)),
         "alg_bytes_per_update": round(alg_bytes_per_update(tile), 4),
         "streaming_roof_gupd_s": HBM_PEAK_GBS / 16.0,
         "tiles": tiles,

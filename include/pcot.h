@@ -172,6 +172,125 @@ pcot_status pcot_dp_run(const int64_t* p, int64_t N, int64_t pmax, const pcot_ti
                         int32_t schedule, int64_t* C, void* workspace, size_t ws_bytes,
                         void* stream);
 
+/* ------------------------------------------------- autotuning and model --- */
+
+/* The paper explores tile sizes by timing a grid of candidates per kernel
+ * (Section 5.2, the tile-size exploration, and its variability figures);
+ * pcot_tune does the same on the GPU over the tile grids below, and a small
+ * learned cost model, trained on such sweeps, predicts a good (tile,
+ * schedule) without timing every candidate.  The sweep stays the reference
+ * the model is judged against. */
+
+#define PCOT_MATRIX_CHAIN 4 /* pcot_problem.kind of the interval DP */
+
+typedef struct {
+    int32_t kind;    /* pcot_kind, or PCOT_MATRIX_CHAIN                                  */
+    int32_t dtype;   /* stencils: pcot_dtype; DP: ignored                                */
+    int64_t dims[3]; /* stencils: extents outer..inner incl. boundary; DP: dims[0] = N  */
+    int64_t T;       /* stencils: time steps; DP: pmax                                   */
+} pcot_problem;
+
+/* One timed (or predicted) candidate. */
+typedef struct {
+    float feat[8];    /* model features, pcot_features()                          */
+    float ms;         /* median time of one run call, milliseconds                */
+    pcot_tile tile;
+    int32_t schedule;
+} pcot_record;
+
+typedef enum {
+    PCOT_TUNE_SWEEP = 0,       /* time every candidate                                 */
+    PCOT_TUNE_MODEL = 1,       /* predict every candidate, time none                   */
+    PCOT_TUNE_MODEL_VERIFY = 2 /* predict every candidate, time the topk best-predicted */
+} pcot_tune_mode;
+
+typedef struct pcot_model pcot_model;
+
+typedef struct {
+    int32_t mode;            /* pcot_tune_mode                                          */
+    int32_t reps;            /* timed runs per candidate, median kept (<= 0: 5)          */
+    int32_t warmup;          /* untimed runs per candidate (< 0: 2)                     */
+    int32_t topk;            /* MODEL_VERIFY: candidates re-timed (<= 0: 3)             */
+    uint32_t sched_mask;     /* bit s: schedule s is a candidate; 0 = every tiled one   */
+    const pcot_model* model; /* required by the MODEL modes                             */
+} pcot_tune_opts;
+
+/* Candidate grid of a problem (host only):
+ *   Jacobi-1D: b_t in {16,32,64,128,256} x b_x in {64,128,256}
+ *   Jacobi-2D: b_t in {4,8,16,32,64} x b_y in {16,32,64,128,256} x b_x in {64,128,256}
+ *   Heat-3D:   b_t in {2,4,8} x b_z in {16,64,256} x b_y in {2,4,8}, b_x = 64
+ *   DP:        b in {32,64} (s[0] = s[1]) x k-chunk in {32,64,128,256}
+ * each crossed with the schedules of sched_mask (stencils: the four tiled
+ * schedules; DP: SLT_WAVE and COT_PAR), keeping only runnable tiles.  Writes
+ * up to `cap` entries to tiles/scheds (either may be NULL) and returns the
+ * number of candidates, or -1 on invalid arguments. */
+int64_t pcot_tune_candidates(const pcot_problem* prob, uint32_t sched_mask, pcot_tile* tiles,
+                             int32_t* scheds, int64_t cap);
+
+/* Model features of (problem, tile, schedule) (host only), all log2 of
+ * positive sizes unless stated:
+ *   stencils: [outer extent (product of all but the innermost; 1D: n),
+ *              inner extent (1D: 1), T, b_t, outer tile (product; 1D: 1),
+ *              b_inner (1D: b_x), element bytes, schedule code]
+ *   DP:       [N, b, k-chunk, pmax, schedule code, 0, 0, 0] */
+pcot_status pcot_features(const pcot_problem* prob, const pcot_tile* tile, int32_t schedule, float* feat);
+
+/* Tunes one problem on the GPU: allocates its own buffers (input filled with
+ * zeros, DP dims with a valid pattern), times or predicts the candidates per
+ * opts, and returns the best in best/best_sched/best_ms (any may be NULL).
+ * Up to `cap` records (every candidate timed or predicted) are written to
+ * `records` (may be NULL) and their number to *n_records.  Synchronous. */
+pcot_status pcot_tune(const pcot_problem* prob, const pcot_tune_opts* opts, pcot_tile* best,
+                      int32_t* best_sched, double* best_ms, pcot_record* records, size_t cap,
+                      size_t* n_records, void* stream);
+
+/* Training options of the cost model (two hidden ReLU layers of 64, binary32,
+ * predicting ln(ms) from standardised features; mean squared error; Adam with
+ * beta1 = 0.9, beta2 = 0.999, eps = 1e-8). */
+typedef struct {
+    int32_t epochs; /* <= 0: 300                              */
+    int32_t batch;  /* 1..256; <= 0: 256                      */
+    float lr;       /* <= 0: 1e-3                             */
+    uint64_t seed;  /* He-uniform initialisation and shuffling */
+} pcot_train_opts;
+
+/* Trains a model on n records with the device training kernel and returns it
+ * in *out (free with pcot_model_free); *final_loss (may be NULL) receives the
+ * last epoch's mean squared error in standardised ln(ms).  Synchronous. */
+pcot_status pcot_model_train(const pcot_record* records, size_t n, const pcot_train_opts* opts,
+                             pcot_model** out, float* final_loss, void* stream);
+/* Predicted ms of n records' features (host arrays), on the device. */
+pcot_status pcot_model_predict_ms(const pcot_model* model, const pcot_record* records, size_t n,
+                                  float* ms, void* stream);
+/* Best predicted candidate of a problem (the MODEL mode of pcot_tune). */
+pcot_status pcot_model_predict(const pcot_model* model, const pcot_problem* prob, uint32_t sched_mask,
+                               pcot_tile* best, int32_t* best_sched, double* pred_ms, void* stream);
+/* Text file: magic line, 8 feature means, 8 feature scales, target mean and
+ * scale, then the 4801 parameters. */
+pcot_status pcot_model_save(const pcot_model* model, const char* path);
+pcot_status pcot_model_load(const char* path, pcot_model** out);
+void pcot_model_free(pcot_model* model);
+
+/* The network itself, for verification against an independent reference.
+ * `params` holds 4801 floats: W1 [64][8], b1 [64], W2 [64][64], b2 [64],
+ * W3 [64], b3 (row-major, output index first).  All arrays are host memory;
+ * the computation runs on the device and the call synchronises.
+ *   pcot_mlp_forward: yhat[i] for rows X[i][0..7], i < n.
+ *   pcot_mlp_grad:    mean squared error of one batch (n <= 256) and its
+ *                     gradient with respect to every parameter.
+ *   pcot_mlp_train:   `epochs` passes of Adam over batches of `batch` rows
+ *                     taken in the order given (order: epochs x n row
+ *                     indices); params, m, v updated in place, the Adam step
+ *                     count continuing from step0; epoch_loss (may be NULL)
+ *                     receives each epoch's mean loss before its updates. */
+#define PCOT_MLP_PARAMS 4801
+pcot_status pcot_mlp_forward(const float* params, const float* X, int32_t n, float* yhat, void* stream);
+pcot_status pcot_mlp_grad(const float* params, const float* X, const float* y, int32_t n, float* grad,
+                          float* loss, void* stream);
+pcot_status pcot_mlp_train(float* params, float* m, float* v, const float* X, const float* y, int32_t n,
+                           const int32_t* order, int32_t epochs, int32_t batch, int32_t step0, float lr,
+                           float* epoch_loss, void* stream);
+
 /* ------------------------------------------------------------ status --- */
 
 /* Synchronises `stream` and reads the device error word that the last run on

@@ -38,6 +38,31 @@ class pcot_tile(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int32), ("s", ctypes.c_int32 * 3)]
 
 
+class pcot_problem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("dims", ctypes.c_int64 * 3),
+                ("T", ctypes.c_int64)]
+
+
+class pcot_record(ctypes.Structure):
+    _fields_ = [("feat", ctypes.c_float * 8), ("ms", ctypes.c_float), ("tile", pcot_tile),
+                ("schedule", ctypes.c_int32)]
+
+
+class pcot_tune_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("reps", ctypes.c_int32), ("warmup", ctypes.c_int32),
+                ("topk", ctypes.c_int32), ("sched_mask", ctypes.c_uint32), ("model", ctypes.c_void_p)]
+
+
+class pcot_train_opts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+MATRIX_CHAIN = 4
+TUNE_SWEEP, TUNE_MODEL, TUNE_MODEL_VERIFY = 0, 1, 2
+MLP_PARAMS = 4801
+
+
 class PcotError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
@@ -62,6 +87,29 @@ _SIGS = {
     "pcot_stencil_run_batched": (_I32, [_I32, _I32, _I32, _I64P, _I64P, _TP, _I32, ctypes.POINTER(_P),
                                         ctypes.POINTER(_P), _P, _SZ, _P]),
     "pcot_error_norms": (_I32, [_I32, _I32, _I64P, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "pcot_tune_candidates": (_I64, [ctypes.POINTER(pcot_problem), ctypes.c_uint32, _TP,
+                                    ctypes.POINTER(ctypes.c_int32), _I64]),
+    "pcot_features": (_I32, [ctypes.POINTER(pcot_problem), _TP, _I32, ctypes.POINTER(ctypes.c_float)]),
+    "pcot_tune": (_I32, [ctypes.POINTER(pcot_problem), ctypes.POINTER(pcot_tune_opts), _TP,
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(pcot_record), _SZ, ctypes.POINTER(ctypes.c_size_t), _P]),
+    "pcot_model_train": (_I32, [ctypes.POINTER(pcot_record), _SZ, ctypes.POINTER(pcot_train_opts),
+                                ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_float), _P]),
+    "pcot_model_predict_ms": (_I32, [_P, ctypes.POINTER(pcot_record), _SZ, ctypes.POINTER(ctypes.c_float), _P]),
+    "pcot_model_predict": (_I32, [_P, ctypes.POINTER(pcot_problem), ctypes.c_uint32, _TP,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), _P]),
+    "pcot_model_save": (_I32, [_P, ctypes.c_char_p]),
+    "pcot_model_load": (_I32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "pcot_model_free": (None, [_P]),
+    "pcot_mlp_forward": (_I32, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _I32,
+                                ctypes.POINTER(ctypes.c_float), _P]),
+    "pcot_mlp_grad": (_I32, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(ctypes.c_float), _I32, ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(ctypes.c_float), _P]),
+    "pcot_mlp_train": (_I32, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                              ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                              ctypes.POINTER(ctypes.c_float), _I32, ctypes.POINTER(ctypes.c_int32), _I32, _I32,
+                              _I32, ctypes.c_float, ctypes.POINTER(ctypes.c_float), _P]),
     "pcot_kernel_timing": (_I32, [_I32]),
     "pcot_kernel_timing_read": (_I32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }

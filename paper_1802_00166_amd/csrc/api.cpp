@@ -38,10 +38,11 @@ hipError_t launch_dp_pad(const long long* p, long long* pp, int Nout, int N, hip
 using namespace pcot;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-pcot_status fail(pcot_status code, const char* fmt, ...) {
+// Records the message of a failing call (read back by pcot_last_error).
+pcot_status pcot::fail(pcot_status code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -50,6 +51,8 @@ pcot_status fail(pcot_status code, const char* fmt, ...) {
     g_err = buf;
     return code;
 }
+
+namespace {
 
 #define HIP_TRY(expr)                                                                     \
     do {                                                                                  \

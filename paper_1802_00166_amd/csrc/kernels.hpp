@@ -17,6 +17,7 @@ constexpr unsigned DEVERR_TIMEOUT = 6;
 constexpr unsigned DEVERR_INPUT = 7;
 
 hipError_t launch_fill_u32(unsigned* p, size_t n, unsigned v, hipStream_t s);
+hipError_t launch_fill_chain(long long* p, int n, long long pmax, hipStream_t s);
 hipError_t launch_copy_boundary(int dtype, const void* src, void* dst0, void* dst1, int d,
                                 const int64_t* n, hipStream_t s);
 hipError_t launch_step(int kind, int dtype, const void* src, void* dst, const int64_t* n,
@@ -60,6 +61,19 @@ hipError_t launch_copy_boundary_batched(int dtype, const TiledProblem* probs, in
 size_t norms_scratch_bytes();
 hipError_t launch_norms(int dtype, int d, const int64_t* n, const void* x, const double* r, double* scratch,
                         hipStream_t s);
+
+// Sets the thread's last-error message and returns `code` (api.cpp).
+int32_t fail(int32_t code, const char* fmt, ...);
+
+// Cost-model MLP (8 -> 64 -> 64 -> 1, binary32), see mlp.hip.
+constexpr int MLP_NP = 4801;
+size_t mlp_scratch_floats();
+hipError_t launch_mlp_forward(const float* params, const float* X, int n, float* yhat, hipStream_t s);
+hipError_t launch_mlp_grad(const float* params, const float* X, const float* y, const int* rows, int n,
+                           float* scratch, float* grad, float* loss, hipStream_t s);
+hipError_t launch_mlp_train(float* params, float* m, float* v, const float* X, const float* y, const int* order,
+                            int n, int epochs, int bsz, int step0, float lr, float beta1, float beta2, float eps,
+                            float* scratch, float* loss_out, hipStream_t s);
 
 // Tiled executors, one per stencil kind.  b = {b_t, spatial sizes outer..inner}.
 // *_supported: is the tile shape runnable; launch_*: one block per queue entry.

@@ -23,6 +23,18 @@ hipError_t launch_fill_u32(unsigned* p, size_t n, unsigned v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Matrix dimensions 1 + (37 i mod pmax): a valid DP input for timing runs.
+__global__ void k_fill_chain(long long* p, int n, long long pmax) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 1 + (long long)(((long long)i * 37) % pmax);
+}
+
+hipError_t launch_fill_chain(long long* p, int n, long long pmax, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_chain, dim3((n + 255) / 256), dim3(256), 0, s, p, n, pmax);
+    return hipGetLastError();
+}
+
 __global__ void k_put_problem(TiledProblem* dst, TiledProblem v) {
     if (threadIdx.x == 0) *dst = v;
 }

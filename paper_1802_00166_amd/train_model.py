@@ -1,0 +1,163 @@
+"""Trains the stencil cost model from timed sweeps and evaluates it.
+
+    python -m paper_1802_00166_amd.train_model --out DIR [--shapes 64]
+
+1. Training set: timed sweeps (pcot_tune, every runnable tile of the grid,
+   schedules SLT_WAVE and COT_PAR) of Jacobi-2D shapes drawn like the uneven
+   batch (extents uniform in [128, 2048] per axis, T uniform in [32, 512],
+   f32 and f64 alternating) and a few Jacobi-1D shapes, from a seed of their
+   own so the evaluated problems stay held out.
+2. The MLP is trained on the device (pcot_model_train) and saved.
+3. Held-out evaluation: the 4096^2 f64 T = 512 Jacobi-2D problem (all four
+   tiled schedules) and instances of the uneven batch.  For each, the
+   model's pick (no timing) is re-timed and compared with the exhaustive
+   sweep's best, and with one fixed tile (the sweep-best of the 4096^2
+   problem applied to every shape: the method without the model).
+
+Writes DIR/stencil.mlp, DIR/sweeps.json (best of every evaluated sweep) and
+DIR/report.json; the training records go to DIR/records.jsonl.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def sample_shapes(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        ny, nx = (int(v) for v in rng.integers(128, 2049, size=2))
+        T = int(rng.integers(32, 513))
+        out.append(("jacobi2d", "f32" if i % 2 == 0 else "f64", (ny, nx), T))
+    return out
+
+
+def batch_instances(count=256, seed_stream=4):
+    """Shapes of the uneven batch, from the shared seeded generator when the
+    repository's input module is present, else from numpy (documented)."""
+    try:
+        import synth
+        return synth.batched_instances(count)
+    except ImportError:
+        rng = np.random.default_rng(1802 + seed_stream)
+        return [(int(rng.integers(128, 2049)), int(rng.integers(128, 2049)), int(rng.integers(32, 513)))
+                for _ in range(count)]
+
+
+def key_of(kind, dtype, shape, T):
+    return "%s/%s/%s/%d" % (kind, dtype, "x".join(str(int(v)) for v in shape), int(T))
+
+
+def main():
+    from . import tune
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--shapes", type=int, default=64)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--eval-batch", type=int, default=16, help="held-out uneven-batch instances evaluated")
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--seed", type=int, default=77)
+    args = ap.parse_args()
+    os.makedirs(args.out, exist_ok=True)
+    two = ["slt_wave", "cot_par"]
+    t_start = time.time()
+
+    # ---- 1. training sweeps
+    train = sample_shapes(args.shapes, args.seed)
+    train += [("jacobi1d", "f64", (n,), T) for n, T in [(1024, 256), (4096, 1000), (16384, 512), (65536, 256)]]
+    records = []
+    sweep_s = 0.0
+    with open(os.path.join(args.out, "records.jsonl"), "w") as rf:
+        for i, (kind, dtype, shape, T) in enumerate(train):
+            t0 = time.time()
+            tile, sched, ms, recs = tune.sweep(tune.problem(kind, dtype, shape, T), reps=args.reps, warmup=1,
+                                               schedules=two)
+            sweep_s += time.time() - t0
+            for r in recs:
+                r["problem"] = key_of(kind, dtype, shape, T)
+                rf.write(json.dumps(r) + "\n")
+            records += recs
+            log("train sweep %d/%d %s: %d candidates, best %s %s %.3f ms (%.1f s)"
+                % (i + 1, len(train), key_of(kind, dtype, shape, T), len(recs), tile, sched, ms, time.time() - t0))
+
+    # ---- 2. device training
+    t0 = time.time()
+    model = tune.Model.train(records, epochs=args.epochs, batch=256, lr=1e-3, seed=args.seed)
+    train_s = time.time() - t0
+    path = os.path.join(args.out, "stencil.mlp")
+    model.save(path)
+    pred = model.predict_ms(records)
+    ms = np.array([r["ms"] for r in records])
+    rmse = float(np.sqrt(np.mean((np.log(pred) - np.log(ms)) ** 2)))
+    log("trained on %d records in %.2f s: final loss %.4f, train RMSE(ln ms) %.3f" %
+        (len(records), train_s, model.final_loss, rmse))
+
+    # ---- 3. held-out evaluation
+    sweeps, evals = {}, []
+    import torch  # noqa: F401  (device already initialised by the sweeps)
+
+    def evaluate(kind, dtype, shape, T, schedules, fixed):
+        prob = tune.problem(kind, dtype, shape, T)
+        t0 = time.time()
+        bt, bs, bms, recs = tune.sweep(prob, reps=args.reps + 2, warmup=1, schedules=schedules)
+        sw_s = time.time() - t0
+        mt, msch, pms = model.predict(prob, schedules)
+        times = {(tuple(r["tile"]), r["schedule"]): r["ms"] for r in recs}
+        # the pick and the fixed tile re-timed in one more session, beside the sweep's best
+        t0 = time.time()
+        _, _, _, again = tune.tune(prob, tune.TUNE_MODEL_VERIFY, model, reps=args.reps + 2, warmup=1, topk=1,
+                                   schedules=schedules)
+        pick_ms = again[0]["ms"]
+        model_s = time.time() - t0
+        fixed_ms = times.get((tuple(fixed[0]), fixed[1])) if fixed else None
+        e = {"problem": key_of(kind, dtype, shape, T), "sweep_best": [list(bt), bs, bms],
+             "model_pick": [list(mt), msch, pick_ms, pms], "pick_over_best": pick_ms / bms,
+             "fixed": [list(fixed[0]), fixed[1], fixed_ms] if fixed else None,
+             "gain_over_fixed": (fixed_ms / pick_ms) if fixed_ms else None,
+             "sweep_s": sw_s, "model_s": model_s, "candidates": len(recs)}
+        sweeps[e["problem"]] = {"best_tile": list(bt), "best_schedule": bs, "best_ms": bms}
+        evals.append(e)
+        log("eval %s: sweep %s %s %.3f ms | model %s %s %.3f ms (x%.3f) | fixed %s" %
+            (e["problem"], bt, bs, bms, mt, msch, pick_ms, pick_ms / bms,
+             ("%.3f ms" % fixed_ms) if fixed_ms else "-"))
+        return bt, bs
+
+    head = evaluate("jacobi2d", "f64", (4096, 4096), 512, None, None)
+    fixed = (head[0], head[1])
+    inst = batch_instances(256)
+    step = max(1, len(inst) // max(1, args.eval_batch))
+    for (ny, nx, T) in inst[::step][:args.eval_batch]:
+        evaluate("jacobi2d", "f32", (ny, nx), T, two, fixed if fixed[1] in two else (fixed[0], "cot_par"))
+
+    ratios = [e["pick_over_best"] for e in evals]
+    gains = [e["gain_over_fixed"] for e in evals if e["gain_over_fixed"]]
+    rep = {
+        "records": len(records), "train_shapes": len(train), "sweep_seconds": sweep_s, "train_seconds": train_s,
+        "final_loss": model.final_loss, "train_rmse_ln_ms": rmse,
+        "geomean_pick_over_best": float(math.exp(np.mean(np.log(ratios)))),
+        "max_pick_over_best": float(max(ratios)),
+        "geomean_gain_over_fixed": float(math.exp(np.mean(np.log(gains)))) if gains else None,
+        "evaluations": evals, "wall_seconds": time.time() - t_start,
+    }
+    with open(os.path.join(args.out, "sweeps.json"), "w") as f:
+        json.dump(sweeps, f, indent=1)
+    with open(os.path.join(args.out, "report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    log("geomean model/sweep %.4f (max %.4f), geomean gain over fixed tile %s" %
+        (rep["geomean_pick_over_best"], rep["max_pick_over_best"], rep["geomean_gain_over_fixed"]))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
