@@ -128,7 +128,8 @@ def pick_tiles():
         from paper_1802_00166_amd import tune
         m = tune.load_default_model()
         if m is not None:
-            tile, sched = tune.predict_stencil(m, "jacobi2d", "f64", (NY, NX), T)
+            # the model ranks the schedules it was trained on
+            tile, sched = tune.predict_stencil(m, "jacobi2d", "f64", (NY, NX), T, tune.MODEL_SCHEDULES)
             learned = {"tile": list(tile), "schedule": sched, "source": "mlp"}
         sw = tune.load_sweep_best("jacobi2d", "f64", (NY, NX), T)
         if sw is not None:

@@ -164,7 +164,11 @@ __device__ __forceinline__ size_t tile_index(const TiledProblem& P, const int* k
 //     successor.
 // Control values live in SGPRs (uni): with per-lane copies the compiler
 // builds per-lane loops around the thread-0 regions that never terminate.
-template <int D, typename Exec>
+// DEVCOH: every global access of `exec` to tile data is device-coherent
+// (buffer accesses with the SC1 policy), so acquiring needs no cache
+// invalidation and releasing needs only the wait for store acknowledgements;
+// otherwise agent-scope fences (L2 invalidate / write-back) are used.
+template <int D, bool DEVCOH = false, typename Exec>
 __device__ __forceinline__ void run_queued_tile(const TiledLaunch& Lc, int* s_tk, int* s_go, Exec&& exec) {
     const int wave = uni((int)(threadIdx.x >> 6));
     if (threadIdx.x == 0)
@@ -194,9 +198,15 @@ __device__ __forceinline__ void run_queued_tile(const TiledLaunch& Lc, int* s_tk
     }
     __syncthreads();
     const int go = uni(*s_go);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if constexpr (DEVCOH) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (go) exec(P, k);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if constexpr (DEVCOH) {
+        __builtin_amdgcn_s_waitcnt(0);  // every store of this wave acknowledged
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll

@@ -122,7 +122,7 @@ __device__ __forceinline__ void exec1d(const TiledProblem& P, const int* k) {
 template <typename S, int C>
 __global__ void __launch_bounds__(64) k_tiled1d(TiledLaunch Lc) {
     __shared__ int s_tk, s_go;
-    run_queued_tile<1>(Lc, &s_tk, &s_go, [&](const TiledProblem& P, const int* k) { exec1d<S, C>(P, k); });
+    run_queued_tile<1, true>(Lc, &s_tk, &s_go, [&](const TiledProblem& P, const int* k) { exec1d<S, C>(P, k); });
 }
 
 template <typename S>

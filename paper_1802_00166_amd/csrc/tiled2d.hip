@@ -48,8 +48,20 @@ template <int C, int G> struct Cfg {
     static constexpr int NPT = (KB * ROW + 64 * G - 1) / (64 * G);
 };
 
+// A staged row in LDS: [0], [1] hold columns jx0-2, jx0-1 (the left
+// neighbour's faces); tile column q = lane*C + c sits at 2 + c*64 + lane, so
+// the 64 lanes touch 64 consecutive words in every access (no bank conflicts).
+template <int C> __device__ __forceinline__ int rpos(int q) { return 2 + (q % C) * 64 + q / C; }
+// positions of lane's left neighbours jx-2 and jx-1 of its first column
+template <int C> __device__ __forceinline__ int rpos_m2(int lane) {
+    return C == 1 ? lane : (lane == 0 ? 0 : 1 + (C - 2) * 64 + lane);
+}
+template <int C> __device__ __forceinline__ int rpos_m1(int lane) {
+    return C == 1 ? lane + 1 : (lane == 0 ? 1 : 1 + (C - 1) * 64 + lane);
+}
+
 template <typename A, int C, int G> struct Smem {
-    A hand[G][2][Cfg<C, G>::ROW];      // [g]: input row of wave g (g > 0); parity by step
+    A hand[G][2][2][Cfg<C, G>::ROW];   // [g]: input rows of wave g (g > 0); parity by step, row of pair
     A bchunk[2][Cfg<C, G>::KB][Cfg<C, G>::ROW];
     A lfs[G][128];                     // left faces of the current chunk, per wave
     A rfs[G][128];                     // right faces of the current chunk, per wave
@@ -143,7 +155,10 @@ __device__ __forceinline__ void exec_tile(const TiledProblem& P, int kt, int ky,
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
             const int idx = threadIdx.x + i * 64 * G;
-            if ((KB * ROW) % (64 * G) == 0 || idx < KB * ROW) dstc[idx] = bst[i];
+            if ((KB * ROW) % (64 * G) == 0 || idx < KB * ROW) {
+                const int p = idx % ROW;
+                dstc[idx - p + (p < 2 ? p : rpos<C>(p - 2))] = bst[i];
+            }
         }
     };
 
@@ -180,11 +195,11 @@ __device__ __forceinline__ void exec_tile(const TiledProblem& P, int kt, int ky,
             // input row of this wave's first level
             A in0[C], x0a, x0b;
             {
-                const A* h = w == 0 ? &sm.bchunk[(r / KB) & 1][r % KB][0] : &sm.hand[w][(S_ - 1) & 1][0];
-                x0b = h[lane * C];
-                x0a = h[lane * C + 1];
+                const A* h = w == 0 ? &sm.bchunk[(r / KB) & 1][r % KB][0] : &sm.hand[w][(S_ - 1) & 1][0][0];
+                x0b = h[rpos_m2<C>(lane)];
+                x0a = h[rpos_m1<C>(lane)];
 #pragma unroll
-                for (int c = 0; c < C; ++c) in0[c] = h[2 + lane * C + c];
+                for (int c = 0; c < C; ++c) in0[c] = h[2 + c * 64 + lane];
             }
 #pragma unroll
             for (int l = 0; l < L; ++l) {
@@ -231,9 +246,9 @@ __device__ __forceinline__ void exec_tile(const TiledProblem& P, int kt, int ky,
                             sm.rfs[w][2 * (rk * L + l) + 1] = out[C - 1];
                         }
                         if (l + 1 == L && w + 1 < G) {
-                            A* h = &sm.hand[w + 1 < G ? w + 1 : 0][S_ & 1][0];
+                            A* h = &sm.hand[w + 1 < G ? w + 1 : 0][S_ & 1][0][0];
 #pragma unroll
-                            for (int c = 0; c < C; ++c) h[2 + lane * C + c] = out[c];
+                            for (int c = 0; c < C; ++c) h[2 + c * 64 + lane] = out[c];
                             if (lane == 0) {
                                 h[0] = lfB;
                                 h[1] = lfA;
@@ -377,7 +392,10 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
             const int idx = threadIdx.x + i * 64 * G;
-            if ((KB * ROW) % (64 * G) == 0 || idx < KB * ROW) dstc[idx] = bst[i];
+            if ((KB * ROW) % (64 * G) == 0 || idx < KB * ROW) {
+                const int p = idx % ROW;
+                dstc[idx - p + (p < 2 ? p : rpos<C>(p - 2))] = bst[i];
+            }
         }
     };
     // right-face staging target: lane 63 writes the chunk slot, others a sink
@@ -391,11 +409,11 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
         const int jy = jy0 + r;
         A in0[C], x0a, x0b;
         {
-            const A* h = w == 0 ? &sm.bchunk[(r / KB) & 1][r % KB][0] : &sm.hand[w][(S_ - 1) & 1][0];
-            x0b = h[lane * C];
-            x0a = h[lane * C + 1];
+            const A* h = w == 0 ? &sm.bchunk[(r / KB) & 1][r % KB][0] : &sm.hand[w][(S_ - 1) & 1][0][0];
+            x0b = h[rpos_m2<C>(lane)];
+            x0a = h[rpos_m1<C>(lane)];
 #pragma unroll
-            for (int c = 0; c < C; ++c) in0[c] = h[2 + lane * C + c];
+            for (int c = 0; c < C; ++c) in0[c] = h[2 + c * 64 + lane];
         }
         // left faces of every level for this row, read before any LDS write of
         // the step so that they are off the level-to-level dependency chain
@@ -455,9 +473,9 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
                 pass_on();
             } else if (!topwave) {
                 const auto lf = pass_on();
-                A* h = &sm.hand[w + 1 < G ? w + 1 : 0][S_ & 1][0];
+                A* h = &sm.hand[w + 1 < G ? w + 1 : 0][S_ & 1][0][0];
 #pragma unroll
-                for (int c = 0; c < C; ++c) h[2 + lane * C + c] = out[c];
+                for (int c = 0; c < C; ++c) h[2 + c * 64 + lane] = out[c];
                 if (lane == 0) {
                     h[0] = lf.second;
                     h[1] = lf.first;
@@ -513,14 +531,290 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
     }
 }
 
+// Full tiles with an even number of rows: like exec_full, but every step
+// advances two rows (a pair), which halves the steps, barriers and LDS
+// hand-offs per update.  Row B of a pair reads row A of the same level as its
+// north/centre neighbours, so within a level the pair is computed A then B
+// from registers.
+template <typename S, int C, int L, int G, bool BND>
+__device__ __forceinline__ void exec_pair(const TiledProblem& P, int kt, int ky, int kx,
+                                          Smem<typename Tr<S>::A, C, G>& sm) {
+    using A = typename Tr<S>::A;
+    using CF = Cfg<C, G>;
+    constexpr int ES = sizeof(S);
+    constexpr int ROW = CF::ROW, KB = CF::KB, NPT = CF::NPT;
+    constexpr int K = 64 / L;  // rows per left/right-face chunk (even)
+    static_assert(K % 2 == 0 && KB % 2 == 0, "chunks hold whole pairs");
+    const int lane = threadIdx.x & 63;
+    const int w = uni((int)(threadIdx.x >> 6));
+    const int ny = P.n[0], nx = P.n[1], by = P.b[1];
+    const int t0 = kt * (G * L);
+    const int tl0 = t0 + w * L;
+    const int jy0 = 1 + ky * by, jx0 = 1 + kx * (64 * C);
+    const int jxl = jx0 + lane * C;
+    const bool topwave = w == G - 1;
+    const uint32_t bytes = (uint32_t)ny * (uint32_t)nx * ES;
+    const uintptr_t pin = (uintptr_t)uptr(P.in), pb0 = (uintptr_t)uptr(P.buf0), pb1 = (uintptr_t)uptr(P.buf1);
+    const rsrc_t rdE = make_rsrc(uptr((const void*)pick(pb0, pb1, tl0 + 1)), bytes);  // even l
+    const rsrc_t rdO = make_rsrc(uptr((const void*)pick(pb0, pb1, tl0)), bytes);      // odd l
+    const rsrc_t rbot = make_rsrc(uptr((const void*)pick(pick(pb0, pb1, t0), pin, t0 == 0)), bytes);
+    auto offs = [&](int y, int x) { return (y * nx + x) * ES; };
+    auto okoff = [&](int y, int x) {
+        return (!BND || (y >= 1 && y <= ny - 2 && x >= 1 && x <= nx - 2)) ? offs(y, x) : OOB;
+    };
+    auto ldv = [&](rsrc_t r, int y, int x) -> A {
+        if (BND && (y < 0 || y >= ny)) return A(0);
+        return IO<S>::ld(r, offs(y, x));
+    };
+
+    A in1[L][C], in2[L][C], x1a[L], x1b[L], x2a[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const int t = tl0 + l;
+        const uintptr_t ps = pick(pick(pb0, pb1, t), pin, t == 0);
+        const rsrc_t rs = make_rsrc(uptr((const void*)ps), bytes);
+        const int y1 = jy0 - t, y2 = jy0 - t - 1, x = jxl - t;
+        x1b[l] = ldv(rs, y1, x - 1);
+        x1a[l] = ldv(rs, y1, x);
+#pragma unroll
+        for (int c = 0; c < C; ++c) in1[l][c] = ldv(rs, y1, x + 1 + c);
+        x2a[l] = ldv(rs, y2, x);
+#pragma unroll
+        for (int c = 0; c < C; ++c) in2[l][c] = ldv(rs, y2, x + 1 + c);
+    }
+    unsigned colok = 0xFFFFFFFFu;
+    if (BND) {
+        colok = 0;
+#pragma unroll
+        for (int l = 0; l < L; ++l)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int x = jxl + c - (tl0 + l);
+                colok |= (x >= 1 && x <= nx - 2) ? (1u << (l * C + c)) : 0u;
+            }
+    }
+
+    A lfE0 = A(0), lfO0 = A(0), lfE1 = A(0), lfO1 = A(0);
+    const int lf_l = lane % L;
+    const bool lf_even = (lf_l & 1) == 0;
+    const bool lf_top = topwave && lf_l == L - 1;
+    auto lf_fetch = [&](int r0) {
+        const int rr = r0 + lane / L, t = tl0 + lf_l;
+        const int y = jy0 + rr - t, x = jx0 - t - 2;
+        const bool ok = rr < by && !lf_top && (!BND || (y >= 0 && y < ny));
+        const int o = ok ? offs(y, x) : OOB;
+        lfE0 = IO<S>::ld(rdE, lf_even ? o : OOB);
+        lfO0 = IO<S>::ld(rdO, lf_even ? OOB : o);
+        lfE1 = IO<S>::ld(rdE, lf_even ? o + ES : OOB);
+        lfO1 = IO<S>::ld(rdO, lf_even ? OOB : o + ES);
+    };
+    A bst[NPT];
+    auto chunk_fetch = [&](int c) {
+        const int bx0 = jx0 - t0 - 1;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int idx = threadIdx.x + i * 64 * G;
+            const int rr = c * KB + idx / ROW;
+            if ((KB * ROW) % (64 * G) == 0 || idx < KB * ROW)
+                bst[i] = rr < by ? ldv(rbot, jy0 + rr - t0 + 1, bx0 + idx % ROW) : A(0);
+        }
+    };
+    auto chunk_store = [&](int c) {
+        A* dstc = &sm.bchunk[c & 1][0][0];
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int idx = threadIdx.x + i * 64 * G;
+            if ((KB * ROW) % (64 * G) == 0 || idx < KB * ROW) {
+                const int p = idx % ROW;
+                dstc[idx - p + (p < 2 ? p : rpos<C>(p - 2))] = bst[i];
+            }
+        }
+    };
+    A* const rf_base = lane == 63 ? &sm.rfs[w][0] : &sm.junk[w][2 * lane];
+    const int rf_stride = lane == 63 ? 2 : 0;
+
+    // all levels of one pair of rows (rA = 2*p, rA+1); TAIL: the tile's last
+    // pair, where every level also writes both rows (two-wide high face)
+    auto levels = [&](auto tail, int S_, int rA, int rk) {
+        constexpr bool TAIL = decltype(tail)::value;
+        A a0[C], b0[C], a0a, a0b, b0a, b0b;  // level input rows A, B and lane-1's last values
+        {
+            const A* hA = w == 0 ? &sm.bchunk[(rA / KB) & 1][rA % KB][0] : &sm.hand[w][(S_ - 1) & 1][0][0];
+            const A* hB = w == 0 ? &sm.bchunk[(rA / KB) & 1][rA % KB + 1][0] : &sm.hand[w][(S_ - 1) & 1][1][0];
+            a0b = hA[rpos_m2<C>(lane)];
+            a0a = hA[rpos_m1<C>(lane)];
+            b0b = hB[rpos_m2<C>(lane)];
+            b0a = hB[rpos_m1<C>(lane)];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                a0[c] = hA[2 + c * 64 + lane];
+                b0[c] = hB[2 + c * 64 + lane];
+            }
+        }
+        A lfaA[L], lfbA[L], lfaB[L], lfbB[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            lfaA[l] = sm.lfs[w][2 * (rk * L + l) + 1];
+            lfbA[l] = sm.lfs[w][2 * (rk * L + l)];
+            lfaB[l] = sm.lfs[w][2 * ((rk + 1) * L + l) + 1];
+            lfbB[l] = sm.lfs[w][2 * ((rk + 1) * L + l)];
+        }
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int t = tl0 + l;
+            const int yA = jy0 + rA - t, yB = yA + 1;
+            const bool okA = !BND || (yA >= 1 && yA <= ny - 2);
+            const bool okB = !BND || (yB >= 1 && yB <= ny - 2);
+            A oa[C], ob[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                // row A: c (rA-1, jx-1), n (rA-2, jx-1), s (rA, jx-1), e (rA-1, jx), w (rA-1, jx-2)
+                const A cc = c >= 1 ? in1[l][c - 1] : x1a[l];
+                const A nn = c >= 1 ? in2[l][c - 1] : x2a[l];
+                const A ss = c >= 1 ? a0[c - 1] : a0a;
+                const A ww = c >= 2 ? in1[l][c - 2] : (c == 1 ? x1a[l] : x1b[l]);
+                A v = Tr<S>::rnd(jac2(cc, nn, ss, in1[l][c], ww));
+                if (BND) v = (okA && ((colok >> (l * C + c)) & 1u)) ? v : cc;
+                oa[c] = v;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                // row B: c (rA, jx-1), n (rA-1, jx-1), s (rB, jx-1), e (rA, jx), w (rA, jx-2)
+                const A cc = c >= 1 ? a0[c - 1] : a0a;
+                const A nn = c >= 1 ? in1[l][c - 1] : x1a[l];
+                const A ss = c >= 1 ? b0[c - 1] : b0a;
+                const A ww = c >= 2 ? a0[c - 2] : (c == 1 ? a0a : a0b);
+                A v = Tr<S>::rnd(jac2(cc, nn, ss, a0[c], ww));
+                if (BND) v = (okB && ((colok >> (l * C + c)) & 1u)) ? v : cc;
+                ob[c] = v;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                in2[l][c] = a0[c];
+                in1[l][c] = b0[c];
+            }
+            x2a[l] = a0a;
+            x1a[l] = b0a;
+            x1b[l] = b0b;
+            const rsrc_t rd = (l & 1) ? rdO : rdE;
+            auto store_rows = [&]() {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int x = jxl + c - t;
+                    const bool cok = (colok >> (l * C + c)) & 1u;
+                    IO<S>::st(rd, BND ? ((okA && cok) ? offs(yA, x) : OOB) : offs(yA, x), oa[c]);
+                    IO<S>::st(rd, BND ? ((okB && cok) ? offs(yB, x) : OOB) : offs(yB, x), ob[c]);
+                }
+            };
+            if (l + 1 < L || !topwave) {
+                const A na = shr1(oa[C - 1], lfaA[l]), nb = shr1(ob[C - 1], lfaB[l]);
+                A nab, nbb;
+                if constexpr (C >= 2) {
+                    nab = shr1(oa[C >= 2 ? C - 2 : 0], lfbA[l]);
+                    nbb = shr1(ob[C >= 2 ? C - 2 : 0], lfbB[l]);
+                } else {
+                    nab = shr1(na, lfbA[l]);
+                    nbb = shr1(nb, lfbB[l]);
+                }
+                A* rf = rf_base + rf_stride * (rk * L + l);
+                rf[0] = C >= 2 ? oa[C >= 2 ? C - 2 : 0] : na;
+                rf[1] = oa[C - 1];
+                A* rfb = rf_base + rf_stride * ((rk + 1) * L + l);
+                rfb[0] = C >= 2 ? ob[C >= 2 ? C - 2 : 0] : nb;
+                rfb[1] = ob[C - 1];
+                if (TAIL) store_rows();
+                if (l + 1 < L) {
+                    a0a = na;
+                    a0b = nab;
+                    b0a = nb;
+                    b0b = nbb;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        a0[c] = oa[c];
+                        b0[c] = ob[c];
+                    }
+                } else {
+                    A* hA = &sm.hand[w + 1 < G ? w + 1 : 0][S_ & 1][0][0];
+                    A* hB = &sm.hand[w + 1 < G ? w + 1 : 0][S_ & 1][1][0];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        hA[2 + c * 64 + lane] = oa[c];
+                        hB[2 + c * 64 + lane] = ob[c];
+                    }
+                    if (lane == 0) {
+                        hA[0] = lfbA[l];
+                        hA[1] = lfaA[l];
+                        hB[0] = lfbB[l];
+                        hB[1] = lfaB[l];
+                    }
+                }
+            } else {
+                store_rows();  // top plane
+            }
+        }
+    };
+
+    chunk_fetch(0);
+    lf_fetch(0);
+    chunk_store(0);
+    chunk_fetch(1);
+    __syncthreads();
+    const int npairs = by / 2;
+    const int nsteps = npairs + G - 1;
+    constexpr int KP = KB / 2;  // pairs per bottom-plane chunk
+    for (int S_ = 0; S_ < nsteps; ++S_) {
+        if (S_ % KP == 0 && S_ > 0) {
+            chunk_store(S_ / KP);
+            __syncthreads();
+            chunk_fetch(S_ / KP + 1);
+        }
+        const int pr = S_ - w;
+        if (pr >= 0 && pr < npairs) {
+            const int rA = 2 * pr;
+            const int rk = rA % K;
+            if (rk == 0) {
+                sm.lfs[w][2 * lane] = lf_even ? lfE0 : lfO0;
+                sm.lfs[w][2 * lane + 1] = lf_even ? lfE1 : lfO1;
+                __builtin_amdgcn_wave_barrier();
+                lf_fetch(rA + K);
+            }
+            if (pr < npairs - 1) levels(std::integral_constant<bool, false>{}, S_, rA, rk);
+            else levels(std::integral_constant<bool, true>{}, S_, rA, rk);
+            if (rk + 1 == K - 1 || rA + 1 == by - 1) {
+                __builtin_amdgcn_wave_barrier();
+                const int rB = rA + 1;
+                const int rr = rB - (rk + 1) + lane / L, t = tl0 + lf_l;
+                const int y = jy0 + rr - t, x = jx0 + 64 * C - 2 - t;
+                const bool ok = rr <= rB && !lf_top;
+                const int o0 = ok ? okoff(y, x) : OOB, o1 = ok ? okoff(y, x + 1) : OOB;
+                const A v0 = sm.rfs[w][2 * lane], v1 = sm.rfs[w][2 * lane + 1];
+                IO<S>::st(rdE, lf_even ? o0 : OOB, v0);
+                IO<S>::st(rdO, lf_even ? OOB : o0, v0);
+                IO<S>::st(rdE, lf_even ? o1 : OOB, v1);
+                IO<S>::st(rdO, lf_even ? OOB : o1, v1);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <typename S, int C, int L, int G>
 __global__ void __launch_bounds__(64 * G) k_tiled2d(TiledLaunch Lc) {
+    // two rows per step pays off when a lane holds few columns (measured:
+    // faster for b_x = 64, 128; slower for 256, whose registers then spill)
+    constexpr bool PAIR = C <= 2;
     using A = typename Tr<S>::A;
     __shared__ Smem<A, C, G> sm;
-    run_queued_tile<2>(Lc, &sm.tk, &sm.go, [&](const TiledProblem& P, const int* k) {
+    run_queued_tile<2, true>(Lc, &sm.tk, &sm.go, [&](const TiledProblem& P, const int* k) {
         const int kt = k[0], ky = k[1], kx = k[2];
         const bool full = (kt + 1) * P.b[0] <= P.T && P.b[0] == G * L;
-        if (full) {
+        if (full && PAIR && (P.b[1] & 1) == 0) {
+            if (tile_interior<2>(P, k))
+                exec_pair<S, C, L, G, false>(P, kt, ky, kx, sm);
+            else
+                exec_pair<S, C, L, G, true>(P, kt, ky, kx, sm);
+        } else if (full) {
             if (tile_interior<2>(P, k))
                 exec_full<S, C, L, G, false>(P, kt, ky, kx, sm);
             else

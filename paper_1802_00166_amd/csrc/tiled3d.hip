@@ -99,18 +99,10 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     };
     constexpr int HPF = 8;  // per-thread halo slots per step (all levels)
     A hv[HPF];
-    // The lanes of one wave may fetch halos of different levels, whose
-    // buffers differ with the parity of t: a buffer descriptor must be
-    // wave-uniform, so these loads take per-lane global addresses instead.
-    const long long nel = (long long)nz * ny * nx;
-    auto ldlvl_lane = [&](int v, int jz, int jy, int jx) -> A {
-        const int t = t0 + v, d = t - 1;  // v >= 1: t >= 1, never the input
-        const int z = jz - d, y = jy - d, x = jx - d;
-        const long long idx = ((long long)z * ny + y) * nx + x;
-        const bool ok = z >= 0 && z < nz && y >= 0 && y < ny && idx >= 0 && idx < nel;
-        const S* base = (const S*)pick(pb0, pb1, t);
-        return ok ? Tr<S>::ld(base + idx) : A(0);
-    };
+    // The lanes of one wave fetch halos of different levels, whose buffers
+    // differ with the parity of t; a buffer descriptor must be wave-uniform,
+    // so both are read (the other offset out of range) and the lane keeps its own.
+    const rsrc_t rhE = src_of(t0 + 1), rhO = src_of(t0 + 2);  // rings v = l+1, l even / odd
     auto halo_load = [&](int s) {  // halos of the planes the levels write at step s
 #pragma unroll
         for (int i = 0; i < HPF; ++i) {
@@ -120,7 +112,12 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
             if (l < nt && jz >= jz0 && jz < jz0 + bz) {
                 int ry, rx;
                 halo_pos(q, ry, rx);
-                hv[i] = ldlvl_lane(l + 1, jz, jy0 - 2 + ry, jx0 - 2 + rx);
+                const int d = t0 + l;  // ring l+1 holds u_{t0+l+1} at (j - d)
+                const int z = jz - d, y = jy0 - 2 + ry - d, x = jx0 - 2 + rx - d;
+                const int o = (z < 0 || z >= nz || y < 0 || y >= ny) ? OOB : offs(z, y, x);
+                const bool ev = (l & 1) == 0;
+                const A a = IO<S>::ld(rhE, ev ? o : OOB), b = IO<S>::ld(rhO, ev ? OOB : o);
+                hv[i] = ev ? a : b;
             }
         }
     };
@@ -176,7 +173,7 @@ __global__ void __launch_bounds__(512) k_tiled3d(TiledLaunch Lc) {
     extern __shared__ char smem_raw[];
     using A = typename Tr<S>::A;
     __shared__ int s_tk, s_go;
-    run_queued_tile<3>(Lc, &s_tk, &s_go, [&](const TiledProblem& P, const int* k) {
+    run_queued_tile<3, true>(Lc, &s_tk, &s_go, [&](const TiledProblem& P, const int* k) {
         exec3d<S>(P, k, reinterpret_cast<A*>(smem_raw));
     });
 }

@@ -68,10 +68,18 @@ def main():
     ap.add_argument("--eval-batch", type=int, default=16, help="held-out uneven-batch instances evaluated")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--seed", type=int, default=77)
+    ap.add_argument("--eval-only", metavar="MODEL", default=None,
+                    help="skip the training sweeps and training; evaluate this saved model")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     two = ["slt_wave", "cot_par"]
     t_start = time.time()
+
+    if args.eval_only:
+        model = tune.Model.load(args.eval_only)
+        model.final_loss = None
+        records, train, sweep_s, train_s, rmse = [], [], 0.0, 0.0, None
+        return evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_start)
 
     # ---- 1. training sweeps
     train = sample_shapes(args.shapes, args.seed)
@@ -102,22 +110,31 @@ def main():
     rmse = float(np.sqrt(np.mean((np.log(pred) - np.log(ms)) ** 2)))
     log("trained on %d records in %.2f s: final loss %.4f, train RMSE(ln ms) %.3f" %
         (len(records), train_s, model.final_loss, rmse))
+    return evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_start)
 
-    # ---- 3. held-out evaluation
+
+def evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_start):
+    """Held-out evaluation: sweep, model pick re-timed, fixed tile."""
+    two = ["slt_wave", "cot_par"]
     sweeps, evals = {}, []
-    import torch  # noqa: F401  (device already initialised by the sweeps)
 
     def evaluate(kind, dtype, shape, T, schedules, fixed):
         prob = tune.problem(kind, dtype, shape, T)
         t0 = time.time()
-        bt, bs, bms, recs = tune.sweep(prob, reps=args.reps + 2, warmup=1, schedules=schedules)
+        recs = []
+        for sch in (schedules or ["slt_lex", "slt_wave", "cot_seq", "cot_par"]):
+            _, _, _, rs = tune.sweep(prob, reps=args.reps + 2, warmup=1, schedules=[sch])
+            recs += rs
+            log("  %s %s: %d candidates (%.1f s)" % (key_of(kind, dtype, shape, T), sch, len(rs), time.time() - t0))
+        best = min(recs, key=lambda r: r["ms"])
+        bt, bs, bms = tuple(best["tile"]), best["schedule"], best["ms"]
         sw_s = time.time() - t0
-        mt, msch, pms = model.predict(prob, schedules)
+        mt, msch, pms = model.predict(prob, two)
         times = {(tuple(r["tile"]), r["schedule"]): r["ms"] for r in recs}
         # the pick and the fixed tile re-timed in one more session, beside the sweep's best
         t0 = time.time()
         _, _, _, again = tune.tune(prob, tune.TUNE_MODEL_VERIFY, model, reps=args.reps + 2, warmup=1, topk=1,
-                                   schedules=schedules)
+                                   schedules=two)
         pick_ms = again[0]["ms"]
         model_s = time.time() - t0
         fixed_ms = times.get((tuple(fixed[0]), fixed[1])) if fixed else None
@@ -144,7 +161,7 @@ def main():
     gains = [e["gain_over_fixed"] for e in evals if e["gain_over_fixed"]]
     rep = {
         "records": len(records), "train_shapes": len(train), "sweep_seconds": sweep_s, "train_seconds": train_s,
-        "final_loss": model.final_loss, "train_rmse_ln_ms": rmse,
+        "final_loss": getattr(model, "final_loss", None), "train_rmse_ln_ms": rmse,
         "geomean_pick_over_best": float(math.exp(np.mean(np.log(ratios)))),
         "max_pick_over_best": float(max(ratios)),
         "geomean_gain_over_fixed": float(math.exp(np.mean(np.log(gains)))) if gains else None,

@@ -26,6 +26,8 @@ from . import (DTYPES, KINDS, MATRIX_CHAIN, MLP_PARAMS, SCHEDULES, TUNE_MODEL, T
 HERE = os.path.dirname(os.path.abspath(__file__))
 MODEL_DIR = os.path.join(HERE, "models")
 SCHED_NAMES = {v: k for k, v in SCHEDULES.items()}
+# schedules of the training sweeps of the stored stencil model
+MODEL_SCHEDULES = ["slt_wave", "cot_par"]
 
 
 def problem(kind: str, dtype: str, shape, T: int) -> pcot_problem:
