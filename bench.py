@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 NY = NX = 4096
 T = 512
 UPDATES = (NY - 2) * (NX - 2) * T
-DEFAULT_TILE = (16, 64, 256)
+DEFAULT_TILE = (32, 64, 256)
 DEFAULT_SCHED = "slt_wave"
 
 HBM_PEAK_GBS = 8000.0
@@ -158,6 +158,234 @@ def time_runs(pc, torch, x, out, ws, tile, sched, steps, warmup):
     return dt, kms / max(kn, 1)
 
 
+# --------------------------------------------------------------- workloads ---
+# The other configurations of the hot path, selected with --workload (the
+# default is the Jacobi-2D headline above).  Same JSON contract; the
+# roofline object describes each one's dominant kernel.
+VALU_OPS_PEAK = 256 * 64 * 2.4e9  # non-fused vector ops/s (f64, and f32 without packed math)
+
+
+def _timed(pc, torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    pc.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kms, kn = pc.kernel_timing_read()
+    pc.kernel_timing(False)
+    return dt, (kms / kn if kn else dt * 1e3)
+
+
+def _roof(updates, kernel_s, bytes_per_update, ops_per_update, ops_peak=VALU_OPS_PEAK, note=None):
+    hbm_roof = HBM_PEAK_GBS * 1e9 / bytes_per_update if bytes_per_update > 0 else float("inf")
+    alu_roof = ops_peak / ops_per_update
+    if hbm_roof <= alu_roof:
+        ach = updates * bytes_per_update / kernel_s / 1e9
+        r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(ach / HBM_PEAK_GBS, 4)}
+    else:
+        ach = updates * ops_per_update / kernel_s / 1e12
+        r = {"bound": "alu", "achieved": round(ach, 3), "peak": round(ops_peak / 1e12, 2), "unit": "TFLOP/s",
+             "frac": round(ach / (ops_peak / 1e12), 4)}
+    r.update({"traffic": None, "alg_bytes_per_update": round(bytes_per_update, 4),
+              "ops_per_update": ops_per_update, "kernel_ms": round(kernel_s * 1e3, 4)})
+    if note:
+        r["note"] = note
+    return r
+
+
+def _record(metric, value, unit, steps, warmup, dt, dtype, data, config, roofline, cpu, higher=True):
+    rec = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": round(dt * 1e3, 4), "higher_is_better": higher, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": data, "config": config, "roofline": roofline}
+    if cpu is not None:
+        rec["cpu_baseline"] = cpu
+    return rec
+
+
+def workload_jacobi1d(args, pc, torch):
+    import synth
+    n, TT, tile, sched = 4096, 1000, (64, 256), "slt_lex"
+    upd = (n - 2) * TT
+    u0 = synth.jacobi1d_input(n)
+    x = torch.from_numpy(u0).to("cuda:0")
+    y = torch.empty_like(x)
+    ws = pc.alloc_workspace(pc.workspace_bytes("jacobi1d", "f64", (n,), TT, tile, sched))
+    dt, kms = _timed(pc, torch, lambda: pc.stencil_run("jacobi1d", "f64", x, TT, tile, sched, out=y, workspace=ws),
+                     args.steps, args.warmup)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            oracle.stencil("jacobi1d", "f64", u0, TT)
+        c = (time.perf_counter() - t0) / reps
+        cpu = {"value": round(upd / c / 1e9, 4), "unit": "GUpdates/s", "cores": 1, "kind": "oracle",
+               "sample": "the whole job (N=4096, T=1000), single-thread plain C loop nest, mean of %d runs" % reps}
+    return _record("GUpdates/s, Jacobi-1D N=4096 FP64, T=1000 (64-step x 256-point time-skewed tiles, lexicographic)",
+                   upd / dt / 1e9, "GUpdates/s", args.steps, args.warmup, dt, "f64",
+                   "synthetic: interior U[0,1) (SplitMix64 stream 1), zero boundary",
+                   {"workload": "jacobi1d_3pt_4096_T1000_f64", "tile_bt_bx": list(tile), "schedule": sched},
+                   _roof(upd, kms / 1e3, 8 * (2.0 / tile[0] + 4.0 / tile[1]), 3,
+                         note="the 32 KiB field stays on chip: bound by latency, not by either roof"), cpu)
+
+
+def workload_heat3d(args, pc, torch, dtype):
+    import numpy as np
+    import synth
+    n, TT = 512, 128
+    tile = {"f64": (2, 32, 8, 64), "f32": (4, 32, 8, 64), "bf16": (4, 32, 8, 64)}[dtype]
+    sched = "slt_wave"
+    upd = (n - 2) ** 3 * TT
+    u = synth.heat3d_input(n)
+    if dtype == "f64":
+        x = torch.from_numpy(u).to("cuda:0")
+    elif dtype == "f32":
+        x = torch.from_numpy(u.astype(np.float32)).to("cuda:0")
+    else:
+        x = torch.from_numpy(synth.to_bf16_bits(u.astype(np.float32)).view(np.int16)).to("cuda:0")
+    y = torch.empty_like(x)
+    ws = pc.alloc_workspace(x.numel() * x.element_size() + (64 << 20))
+    dt, kms = _timed(pc, torch, lambda: pc.stencil_run("heat3d", dtype, x, TT, tile, sched, out=y, workspace=ws),
+                     args.steps, args.warmup)
+    dtn, _ = _timed(pc, torch, lambda: pc.stencil_run("heat3d", dtype, x, TT, None, "naive", out=y, workspace=ws),
+                    1, 1)
+    pc.stencil_run("heat3d", dtype, x, TT, tile, sched, out=y, workspace=ws)
+    torch.cuda.synchronize()
+    err = None
+    if dtype != "f64":
+        # reference: the f64 path on the f64 input (bit-identical to the f64 oracle)
+        x64 = torch.from_numpy(u).to("cuda:0")
+        r64 = torch.empty_like(x64)
+        ws64 = pc.alloc_workspace(x64.numel() * 8 + (64 << 20))
+        pc.stencil_run("heat3d", "f64", x64, TT, (2, 32, 8, 64), sched, out=r64, workspace=ws64)
+        nm = pc.error_norms(dtype, y, r64)
+        err = {"max_rel": nm["max_rel"], "l2_rel": nm["l2_rel"], "reference": "FP64 path (bit-identical to the FP64 oracle)"}
+        del x64, r64, ws64
+    e = {"f64": 8, "f32": 4, "bf16": 2}[dtype]
+    bt, bz, by, bx = tile
+    cpu = None
+    if not args.no_cpu and dtype == "f64":
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        ts = 8
+        t0 = time.perf_counter()
+        oracle.stencil("heat3d", "f64", u, ts, threads=threads)
+        c = time.perf_counter() - t0
+        cpu = {"value": round((n - 2) ** 3 * ts / c / 1e9, 4), "unit": "GUpdates/s", "cores": threads, "kind": "oracle",
+               "sample": "Heat-3D 512^3 f64, %d of the 128 steps, plain C loop nest, %d OpenMP threads, %.2f s"
+                         % (ts, threads, c)}
+    rec = _record("GUpdates/s, Heat-3D 512^3 %s, T=128 (time-skewed tiles)" % dtype.upper(), upd / dt / 1e9,
+                  "GUpdates/s", args.steps, args.warmup, dt, dtype,
+                  "synthetic: interior U[0,1) (SplitMix64 stream 3), zero boundary",
+                  {"workload": "heat3d_7pt_512_T128_%s" % dtype, "tile_bt_bz_by_bx": list(tile), "schedule": sched},
+                  _roof(upd, kms / 1e3, e * (2.0 / bt + 4.0 / bx + 4.0 / by + 4.0 / bz), 11), cpu)
+    rec["naive_gupd_s"] = round(upd / dtn / 1e9, 2)
+    rec["streaming_roof_gupd_s"] = HBM_PEAK_GBS / (2 * e)
+    if err:
+        rec["error_vs_fp64"] = err
+    return rec
+
+
+def workload_matrix_chain(args, pc, torch):
+    import synth
+    N, pmax, tile, sched = 4096, 100, (0, 32, 32, 64), "slt_wave"
+    upd = (N ** 3 - N) // 6
+    p = torch.from_numpy(synth.chain_dims(N)).to("cuda:0")
+    C = torch.empty((N, N), dtype=torch.int64, device="cuda:0")
+    ws = pc.alloc_workspace(pc.dp_workspace_bytes(N, tile, sched))
+    dt, kms = _timed(pc, torch, lambda: pc.dp_run(p, pmax, tile, sched, out=C, workspace=ws), args.steps, args.warmup)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        Ns = 1024
+        ps = synth.chain_dims(Ns)
+        t0 = time.perf_counter()
+        oracle.matrix_chain(ps)
+        c = time.perf_counter() - t0
+        cpu = {"value": round((Ns ** 3 - Ns) / 6 / c / 1e9, 4), "unit": "GUpdates/s", "cores": 1, "kind": "oracle",
+               "sample": "matrix chain N=%d (same generator), single-thread plain C DP, %.2f s" % (Ns, c)}
+    # u32 path: v_mul_u32_u24, v_add3_u32, v_min3_u32 per pair of candidate splits -> 2.5 VALU ops/update
+    return _record("GUpdates/s, matrix-chain interval DP N=4096 (exact), tile diagonals", upd / dt / 1e9,
+                   "GUpdates/s", args.steps, args.warmup, dt, "u32 (exact; int64 API)",
+                   "synthetic: p_i ~ U{1..100} (SplitMix64 stream 5)",
+                   {"workload": "matrix_chain_4096_pmax100", "tile_b_b_kchunk": list(tile[1:]), "schedule": sched},
+                   _roof(upd, kms / 1e3, 2 * 4 / 32, 2.5), cpu)
+
+
+def workload_batched(args, pc, torch):
+    """The uneven batch: 256 f32 instances in one persistent launch, replayed
+    from a HIP graph, with tiles from the cost model (one b_x for the batch)
+    and, for comparison, one fixed tile for every instance."""
+    import numpy as np
+    import synth
+    from paper_1802_00166_amd import tune
+    inst = synth.batched_instances(256)
+    xs = [torch.from_numpy(synth.batched_field(i, ny, nx)).to("cuda:0") for i, (ny, nx, _) in enumerate(inst)]
+    Ts = [TT for (_, _, TT) in inst]
+    shapes = [(ny, nx) for (ny, nx, _) in inst]
+    upd = sum((ny - 2) * (nx - 2) * TT for (ny, nx, TT) in inst)
+    model = tune.load_default_model()
+    fixed = [(16, 64, 128)] * len(inst)
+    choice = {"fixed": fixed}
+    if model is not None:
+        # one b_x for the whole batch (one executor instance): per instance
+        # the best predicted SLT_WAVE candidate of each b_x, then the b_x with
+        # the smallest predicted total
+        per = []
+        for sh, TT in zip(shapes, Ts):
+            prob = tune.problem("jacobi2d", "f32", sh, TT)
+            cands = [c for c in tune.candidates(prob, ["slt_wave"])]
+            ms = model.predict_ms([{"feat": list(tune.features(prob, c[0], c[1])), "tile": list(c[0]),
+                                    "schedule": c[1]} for c in cands])
+            best = {}
+            for c, m in zip(cands, ms):
+                bxc = c[0][2]
+                if bxc not in best or m < best[bxc][1]:
+                    best[bxc] = (tuple(c[0]), m)
+            per.append(best)
+        bx = min((64, 128, 256), key=lambda b: sum(p[b][1] for p in per))
+        choice["model"] = [p[bx][0] for p in per]
+    results = {}
+    for name, tiles in choice.items():
+        outs = [torch.empty_like(x) for x in xs]
+        ws = pc.alloc_workspace(pc.workspace_bytes_batched("jacobi2d", "f32", shapes, Ts, tiles, "slt_wave"))
+        pc.stencil_run_batched("jacobi2d", "f32", xs, Ts, tiles, "slt_wave", outs=outs, workspace=ws)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            pc.stencil_run_batched("jacobi2d", "f32", xs, Ts, tiles, "slt_wave", outs=outs, workspace=ws)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        results[name] = (time.perf_counter() - t0) / args.steps
+        if pc.stream_status(ws) != 0:
+            raise RuntimeError("device error in the batched run: %s" % pc.last_error())
+    best = "model" if "model" in results else "fixed"
+    dt = results[best]
+    rec = _record("GUpdates/s, 256 uneven Jacobi-2D FP32 instances, one persistent launch replayed from a HIP graph",
+                  upd / dt / 1e9, "GUpdates/s", args.steps, args.warmup, dt, "f32",
+                  "synthetic: 256 shapes n_y, n_x ~ U{128..2048}, T ~ U{32..512}, every cell U[0,1) (SplitMix64 stream 4)",
+                  {"workload": "batched_jacobi2d_256_f32", "instances": len(inst), "updates_per_step": upd,
+                   "tiles": best, "schedule": "slt_wave"},
+                  _roof(upd, dt, 4 * (2.0 / 16 + 4.0 / 128 + 4.0 / 64), 5,
+                        note="graph-replay wall time per launch; alg bytes at the fixed tile"), None)
+    rec["graph_replay_ms"] = {k: round(v * 1e3, 3) for k, v in results.items()}
+    if "model" in results:
+        rec["model_over_fixed_speedup"] = round(results["fixed"] / results["model"], 4)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +397,9 @@ def main():
     ap.add_argument("--no-swept", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy used to scale the HBM traffic counters")
+    ap.add_argument("--workload", default="jacobi2d",
+                    choices=["jacobi2d", "jacobi1d", "heat3d_f64", "heat3d_f32", "heat3d_bf16", "matrix_chain",
+                             "batched"])
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
@@ -177,6 +408,19 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
               "(multi-GPU sharding is described in DESIGN.md, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload != "jacobi2d":
+        import torch
+        import paper_1802_00166_amd as pc
+        if args.workload == "jacobi1d":
+            rec = workload_jacobi1d(args, pc, torch)
+        elif args.workload.startswith("heat3d_"):
+            rec = workload_heat3d(args, pc, torch, args.workload.split("_")[1])
+        elif args.workload == "matrix_chain":
+            rec = workload_matrix_chain(args, pc, torch)
+        else:
+            rec = workload_batched(args, pc, torch)
+        print(json.dumps(rec), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -25,17 +25,18 @@ namespace pcot {
 
 namespace {
 
-template <typename S>
+template <typename S, int BY>
 __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, typename Tr<S>::A* lds) {
     using A = typename Tr<S>::A;
     constexpr int ES = sizeof(S);
     constexpr int BX = 64, RX = BX + 2;
     const int lane = threadIdx.x & 63;
     const int w = uni((int)(threadIdx.x >> 6));
-    const int nthr = blockDim.x;
+    constexpr int nthr = 64 * BY;
     const int nz = P.n[0], ny = P.n[1], nx = P.n[2];
-    const int bt = P.b[0], bz = P.b[1], by = P.b[2];
-    const int RY = by + 2, PL = RY * RX;  // plane of the ring, with halo
+    const int bt = P.b[0], bz = P.b[1];
+    constexpr int by = BY;
+    constexpr int RY = by + 2, PL = RY * RX;  // plane of the ring, with halo
     const int t0 = k[0] * bt;
     const int nt = min(bt, P.T - t0);
     const int ttop = t0 + nt - 1;
@@ -73,32 +74,55 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
             ring(v, jz, ry, rx) = ldlvl(v, jz, jy0 - 2 + ry, jx0 - 2 + rx);
         }
     }
-    // prefetch registers: ring-0 plane and the halos of each level's next plane
+    // Prefetch slots: every thread owns fixed positions of the ring-0 plane
+    // and of the halos, so their in-plane offsets are computed once here and
+    // only the plane index changes from step to step.
     constexpr int PF = 4;  // per-thread slots for one ring-0 plane: 4*256 >= 6*66 at by = 4
     A p0[PF];
+    int p_lds[PF], p_xy[PF];  // in-plane LDS index (-1: idle), global row/column offset (-1: outside)
+    const int d0 = t0 - 1;    // ring 0 holds u_t0 at (j - d0)
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+        const int e = threadIdx.x + i * nthr;
+        const int pr = e / RX, pc = e % RX;
+        const int y = jy0 - 2 + pr - d0, x = jx0 - 2 + pc - d0;
+        p_lds[i] = e < PL ? e : -1;
+        p_xy[i] = (y >= 0 && y < ny) ? y * nx + x : -1;
+    }
+    auto gofs = [&](int z, int xy) {  // byte offset of (z, row/column), or OOB outside the array
+        return (z < 0 || z >= nz || xy < 0) ? OOB : (z * ny * nx + xy) * ES;
+    };
+    const rsrc_t r0 = src_of(t0);
     auto pf0_load = [&](int jz) {
 #pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            const int e = threadIdx.x + i * nthr;
-            if (e < PL) p0[i] = ldlvl(0, jz, jy0 - 2 + e / RX, jx0 - 2 + e % RX);
-        }
+        for (int i = 0; i < PF; ++i)
+            if (p_lds[i] >= 0) p0[i] = IO<S>::ld(r0, gofs(jz - d0, p_xy[i]));
     };
     auto pf0_store = [&](int jz) {
+        A* pl = &ring(0, jz, 0, 0);
 #pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            const int e = threadIdx.x + i * nthr;
-            if (e < PL) ring(0, jz, e / RX, e % RX) = p0[i];
-        }
+        for (int i = 0; i < PF; ++i)
+            if (p_lds[i] >= 0) pl[p_lds[i]] = p0[i];
     };
     // halo of plane jz of ring v (v >= 1): rows ry = 0, 1 (all RX columns) and
-    // columns rx = 0, 1 of rows 2..RY-1: 2*RX + 2*by values
-    const int HL = 2 * RX + 2 * by;
-    auto halo_pos = [&](int e, int& ry, int& rx) {
-        if (e < 2 * RX) { ry = e / RX; rx = e % RX; }
-        else { const int q = e - 2 * RX; ry = 2 + q / 2; rx = q & 1; }
-    };
+    // columns rx = 0, 1 of rows 2..RY-1: 2*RX + 2*by values per level
+    constexpr int HL = 2 * RX + 2 * by;
     constexpr int HPF = 8;  // per-thread halo slots per step (all levels)
     A hv[HPF];
+    int h_l[HPF], h_lds[HPF], h_xy[HPF];  // level (nt: idle), in-plane LDS index, global row/column
+#pragma unroll
+    for (int i = 0; i < HPF; ++i) {
+        const int e = threadIdx.x + i * nthr;
+        const int l = min(e / HL, nt), q = e % HL;
+        int ry, rx;
+        if (q < 2 * RX) { ry = q / RX; rx = q % RX; }
+        else { ry = 2 + (q - 2 * RX) / 2; rx = (q - 2 * RX) & 1; }
+        const int d = t0 + l;  // ring l+1 holds u_{t0+l+1} at (j - d)
+        const int y = jy0 - 2 + ry - d, x = jx0 - 2 + rx - d;
+        h_l[i] = l;
+        h_lds[i] = ry * RX + rx;
+        h_xy[i] = (y >= 0 && y < ny) ? y * nx + x : -1;
+    }
     // The lanes of one wave fetch halos of different levels, whose buffers
     // differ with the parity of t; a buffer descriptor must be wave-uniform,
     // so both are read (the other offset out of range) and the lane keeps its own.
@@ -106,15 +130,9 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     auto halo_load = [&](int s) {  // halos of the planes the levels write at step s
 #pragma unroll
         for (int i = 0; i < HPF; ++i) {
-            const int e = threadIdx.x + i * nthr;
-            const int l = e / HL, q = e % HL;
-            const int jz = jz0 + s - l;
-            if (l < nt && jz >= jz0 && jz < jz0 + bz) {
-                int ry, rx;
-                halo_pos(q, ry, rx);
-                const int d = t0 + l;  // ring l+1 holds u_{t0+l+1} at (j - d)
-                const int z = jz - d, y = jy0 - 2 + ry - d, x = jx0 - 2 + rx - d;
-                const int o = (z < 0 || z >= nz || y < 0 || y >= ny) ? OOB : offs(z, y, x);
+            const int l = h_l[i], sl = s - l;
+            if (l < nt && sl >= 0 && sl < bz) {
+                const int o = gofs(jz0 + sl - t0 - l, h_xy[i]);  // z = jz - d
                 const bool ev = (l & 1) == 0;
                 const A a = IO<S>::ld(rhE, ev ? o : OOB), b = IO<S>::ld(rhO, ev ? OOB : o);
                 hv[i] = ev ? a : b;
@@ -124,14 +142,8 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     auto halo_store = [&](int s) {
 #pragma unroll
         for (int i = 0; i < HPF; ++i) {
-            const int e = threadIdx.x + i * nthr;
-            const int l = e / HL, q = e % HL;
-            const int jz = jz0 + s - l;
-            if (l < nt && jz >= jz0 && jz < jz0 + bz) {
-                int ry, rx;
-                halo_pos(q, ry, rx);
-                ring(l + 1, jz, ry, rx) = hv[i];
-            }
+            const int l = h_l[i], sl = s - l;
+            if (l < nt && sl >= 0 && sl < bz) (&ring(l + 1, jz0 + sl, 0, 0))[h_lds[i]] = hv[i];
         }
     };
     pf0_load(jz0 + 1);
@@ -162,20 +174,31 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
             const A out = in ? v : u;
             ring(l + 1, jz, ry, rx) = out;
             const bool face = t == ttop || lane >= BX - 2 || w >= by - 2 || jz >= jz0 + bz - 2;
-            if (face && in) IO<S>::st(src_of(t + 1), offs(z, y, x), out);
+            // level l writes u_{t0+l+1}: the buffers of rings l+1 (hoisted descriptors)
+            if (face && in) IO<S>::st((l & 1) ? rhO : rhE, offs(z, y, x), out);
         }
         __syncthreads();
     }
 }
 
-template <typename S>
-__global__ void __launch_bounds__(512) k_tiled3d(TiledLaunch Lc) {
+template <typename S, int BY>
+__global__ void __launch_bounds__(64 * BY) k_tiled3d(TiledLaunch Lc) {
     extern __shared__ char smem_raw[];
     using A = typename Tr<S>::A;
     __shared__ int s_tk, s_go;
     run_queued_tile<3, true>(Lc, &s_tk, &s_go, [&](const TiledProblem& P, const int* k) {
-        exec3d<S>(P, k, reinterpret_cast<A*>(smem_raw));
+        exec3d<S, BY>(P, k, reinterpret_cast<A*>(smem_raw));
     });
+}
+
+template <typename S, int BY>
+hipError_t launch_by(const TiledLaunch& Lc, size_t lds, hipStream_t s) {
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_tiled3d<S, BY>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_tiled3d<S, BY>), dim3(Lc.nq), dim3(64 * BY), lds, s, Lc);
+    return hipGetLastError();
 }
 
 template <typename S>
@@ -184,12 +207,12 @@ hipError_t launch_dtype(const int* b, const TiledLaunch& Lc, hipStream_t s) {
     using A = typename Tr<S>::A;
     const int bt = b[0], by = b[2];
     const size_t lds = (size_t)(bt + 1) * 4 * (by + 2) * 66 * sizeof(A);
-    if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_tiled3d<S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    switch (by) {
+        case 2: return launch_by<S, 2>(Lc, lds, s);
+        case 4: return launch_by<S, 4>(Lc, lds, s);
+        case 8: return launch_by<S, 8>(Lc, lds, s);
+        default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((k_tiled3d<S>), dim3(Lc.nq), dim3(64 * by), lds, s, Lc);
-    return hipGetLastError();
 }
 
 }  // namespace

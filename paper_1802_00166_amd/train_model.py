@@ -43,6 +43,20 @@ def sample_shapes(n, seed):
     return out
 
 
+def sample_large(n, seed):
+    """Large training shapes, so that 4096-class problems are interpolated
+    rather than extrapolated (the 4096^2, T = 512 problem itself stays held out)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        ny, nx = (int(v) for v in rng.integers(2048, 4097, size=2))
+        T = int(rng.integers(128, 513))
+        if (ny, nx, T) == (4096, 4096, 512):
+            T -= 1
+        out.append(("jacobi2d", "f64" if i % 2 == 0 else "f32", (ny, nx), T))
+    return out
+
+
 def batch_instances(count=256, seed_stream=4):
     """Shapes of the uneven batch, from the shared seeded generator when the
     repository's input module is present, else from numpy (documented)."""
@@ -68,6 +82,12 @@ def main():
     ap.add_argument("--eval-batch", type=int, default=16, help="held-out uneven-batch instances evaluated")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--seed", type=int, default=77)
+    ap.add_argument("--large-shapes", type=int, default=8,
+                    help="extra training shapes with extents in [2048, 4096] (T in [128, 512])")
+    ap.add_argument("--extra-records", default=None,
+                    help="JSON-lines records of earlier training sweeps to train on as well")
+    ap.add_argument("--skip-small", action="store_true",
+                    help="do not sweep the --shapes set (use with --extra-records holding it)")
     ap.add_argument("--eval-only", metavar="MODEL", default=None,
                     help="skip the training sweeps and training; evaluate this saved model")
     args = ap.parse_args()
@@ -82,11 +102,19 @@ def main():
         return evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_start)
 
     # ---- 1. training sweeps
-    train = sample_shapes(args.shapes, args.seed)
-    train += [("jacobi1d", "f64", (n,), T) for n, T in [(1024, 256), (4096, 1000), (16384, 512), (65536, 256)]]
+    train = [] if args.skip_small else sample_shapes(args.shapes, args.seed)
+    if not args.skip_small:
+        train += [("jacobi1d", "f64", (n,), T) for n, T in [(1024, 256), (4096, 1000), (16384, 512), (65536, 256)]]
+    train += sample_large(args.large_shapes, args.seed + 1)
     records = []
+    if args.extra_records:
+        with open(args.extra_records) as f:
+            records = [json.loads(l) for l in f if l.strip()]
+        log("loaded %d earlier records" % len(records))
     sweep_s = 0.0
     with open(os.path.join(args.out, "records.jsonl"), "w") as rf:
+        for r in records:
+            rf.write(json.dumps(r) + "\n")
         for i, (kind, dtype, shape, T) in enumerate(train):
             t0 = time.time()
             tile, sched, ms, recs = tune.sweep(tune.problem(kind, dtype, shape, T), reps=args.reps, warmup=1,
