@@ -319,10 +319,23 @@ def workload_matrix_chain(args, pc, torch):
                    _roof(upd, kms / 1e3, 2 * 4 / 32, 2.5), cpu)
 
 
+def _batch_bytes(tiles, inst):
+    """Update-weighted algorithmic bytes per update of a batch (f32)."""
+    tot = w = 0.0
+    for (bt, by, bx), (ny, nx, TT) in zip(tiles, inst):
+        u = (ny - 2) * (nx - 2) * TT
+        tot += u * 4 * (2.0 / bt + 4.0 / bx + 4.0 / by)
+        w += u
+    return tot / w
+
+
 def workload_batched(args, pc, torch):
     """The uneven batch: 256 f32 instances in one persistent launch, replayed
-    from a HIP graph, with tiles from the cost model (one b_x for the batch)
-    and, for comparison, one fixed tile for every instance."""
+    from a HIP graph.  Tile choices compared: a sweep over uniform tiles (one
+    tile for every instance) and the cost model's per-instance picks (one b_x
+    for the batch).  The model predicts stand-alone runs, which are bound by
+    their critical path; in the batch, throughput binds instead, so the two
+    can disagree: both times are reported and the value is the faster."""
     import numpy as np
     import synth
     from paper_1802_00166_amd import tune
@@ -332,8 +345,9 @@ def workload_batched(args, pc, torch):
     shapes = [(ny, nx) for (ny, nx, _) in inst]
     upd = sum((ny - 2) * (nx - 2) * TT for (ny, nx, TT) in inst)
     model = tune.load_default_model()
-    fixed = [(16, 64, 128)] * len(inst)
-    choice = {"fixed": fixed}
+    uniform = [(16, 64, 128), (32, 64, 128), (16, 64, 256), (32, 64, 256), (16, 32, 128), (32, 32, 256),
+               (16, 128, 256), (64, 64, 128)]
+    choice = {"uniform_%d_%d_%d" % t: [t] * len(inst) for t in uniform}
     if model is not None:
         # one b_x for the whole batch (one executor instance): per instance
         # the best predicted SLT_WAVE candidate of each b_x, then the b_x with
@@ -371,18 +385,19 @@ def workload_batched(args, pc, torch):
         results[name] = (time.perf_counter() - t0) / args.steps
         if pc.stream_status(ws) != 0:
             raise RuntimeError("device error in the batched run: %s" % pc.last_error())
-    best = "model" if "model" in results else "fixed"
+    best = min(results, key=results.get)
     dt = results[best]
     rec = _record("GUpdates/s, 256 uneven Jacobi-2D FP32 instances, one persistent launch replayed from a HIP graph",
                   upd / dt / 1e9, "GUpdates/s", args.steps, args.warmup, dt, "f32",
                   "synthetic: 256 shapes n_y, n_x ~ U{128..2048}, T ~ U{32..512}, every cell U[0,1) (SplitMix64 stream 4)",
                   {"workload": "batched_jacobi2d_256_f32", "instances": len(inst), "updates_per_step": upd,
                    "tiles": best, "schedule": "slt_wave"},
-                  _roof(upd, dt, 4 * (2.0 / 16 + 4.0 / 128 + 4.0 / 64), 5,
-                        note="graph-replay wall time per launch; alg bytes at the fixed tile"), None)
+                  _roof(upd, dt, _batch_bytes(choice[best], inst), 5, note="graph-replay wall time per launch"), None)
     rec["graph_replay_ms"] = {k: round(v * 1e3, 3) for k, v in results.items()}
+    unif = min((k for k in results if k.startswith("uniform")), key=results.get)
+    rec["best_uniform"] = unif
     if "model" in results:
-        rec["model_over_fixed_speedup"] = round(results["fixed"] / results["model"], 4)
+        rec["model_over_best_uniform_time"] = round(results["model"] / results[unif], 4)
     return rec
 
 

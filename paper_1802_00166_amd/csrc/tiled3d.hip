@@ -75,28 +75,34 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
         }
     }
     // Prefetch slots: every thread owns fixed positions of the ring-0 plane
-    // and of the halos, so their in-plane offsets are computed once here and
-    // only the plane index changes from step to step.
-    constexpr int PF = 4;  // per-thread slots for one ring-0 plane: 4*256 >= 6*66 at by = 4
+    // and of the halos.  Their byte offsets and the steps in which they are
+    // live are computed once per tile; a step then costs one add and two
+    // unsigned compares per slot (32-bit multiplies are multi-pass on CDNA).
+    const uint32_t PB = (uint32_t)ny * (uint32_t)nx * ES;  // bytes per plane
+    constexpr int PF = (PL + nthr - 1) / nthr;             // ring-0 plane slots
     A p0[PF];
-    int p_lds[PF], p_xy[PF];  // in-plane LDS index (-1: idle), global row/column offset (-1: outside)
-    const int d0 = t0 - 1;    // ring 0 holds u_t0 at (j - d0)
+    int p_lds[PF];        // in-plane LDS index, -1: idle
+    uint32_t p_off[PF];   // byte offset at step 0 (mod 2^32)
+    bool p_yok[PF];       // row inside the array
+    const int d0 = t0 - 1;  // ring 0 holds u_t0 at (j - d0)
+    // pf0_load(jz0 + s + 2) reads plane z = jz0 + s + 2 - d0: live while 0 <= z < nz
+    const int zc0 = jz0 + 2 - d0;
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
         const int e = threadIdx.x + i * nthr;
         const int pr = e / RX, pc = e % RX;
         const int y = jy0 - 2 + pr - d0, x = jx0 - 2 + pc - d0;
         p_lds[i] = e < PL ? e : -1;
-        p_xy[i] = (y >= 0 && y < ny) ? y * nx + x : -1;
+        p_yok[i] = y >= 0 && y < ny;
+        p_off[i] = (uint32_t)zc0 * PB + (uint32_t)(y * nx + x) * (uint32_t)ES;
     }
-    auto gofs = [&](int z, int xy) {  // byte offset of (z, row/column), or OOB outside the array
-        return (z < 0 || z >= nz || xy < 0) ? OOB : (z * ny * nx + xy) * ES;
-    };
     const rsrc_t r0 = src_of(t0);
-    auto pf0_load = [&](int jz) {
+    auto pf0_load = [&](int s) {  // ring-0 plane jz0 + s + 2
+        const bool zok = (uint32_t)(zc0 + s) < (uint32_t)nz;  // wave-uniform
 #pragma unroll
         for (int i = 0; i < PF; ++i)
-            if (p_lds[i] >= 0) p0[i] = IO<S>::ld(r0, gofs(jz - d0, p_xy[i]));
+            if (p_lds[i] >= 0)
+                p0[i] = IO<S>::ld(r0, (zok && p_yok[i]) ? (int)(p_off[i] + (uint32_t)s * PB) : OOB);
     };
     auto pf0_store = [&](int jz) {
         A* pl = &ring(0, jz, 0, 0);
@@ -107,9 +113,12 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     // halo of plane jz of ring v (v >= 1): rows ry = 0, 1 (all RX columns) and
     // columns rx = 0, 1 of rows 2..RY-1: 2*RX + 2*by values per level
     constexpr int HL = 2 * RX + 2 * by;
-    constexpr int HPF = 8;  // per-thread halo slots per step (all levels)
+    constexpr int HPF = BY == 8 ? 4 : 8;  // halo slots per thread per step (all levels)
     A hv[HPF];
-    int h_l[HPF], h_lds[HPF], h_xy[HPF];  // level (nt: idle), in-plane LDS index, global row/column
+    // level (nt: idle), in-plane LDS index, first step with z >= 0 (far
+    // below any step when the row lies outside the array), offset at step 0
+    int h_l[HPF], h_lds[HPF], h_zlo[HPF];
+    uint32_t h_off[HPF];
 #pragma unroll
     for (int i = 0; i < HPF; ++i) {
         const int e = threadIdx.x + i * nthr;
@@ -119,9 +128,12 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
         else { ry = 2 + (q - 2 * RX) / 2; rx = (q - 2 * RX) & 1; }
         const int d = t0 + l;  // ring l+1 holds u_{t0+l+1} at (j - d)
         const int y = jy0 - 2 + ry - d, x = jx0 - 2 + rx - d;
+        // at step s level l writes plane jz = jz0 + s - l, read at z = jz - d
+        const int zc = jz0 - l - d;
         h_l[i] = l;
         h_lds[i] = ry * RX + rx;
-        h_xy[i] = (y >= 0 && y < ny) ? y * nx + x : -1;
+        h_zlo[i] = (y >= 0 && y < ny) ? -zc : -(1 << 30);
+        h_off[i] = (uint32_t)zc * PB + (uint32_t)(y * nx + x) * (uint32_t)ES;
     }
     // The lanes of one wave fetch halos of different levels, whose buffers
     // differ with the parity of t; a buffer descriptor must be wave-uniform,
@@ -130,9 +142,10 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     auto halo_load = [&](int s) {  // halos of the planes the levels write at step s
 #pragma unroll
         for (int i = 0; i < HPF; ++i) {
-            const int l = h_l[i], sl = s - l;
-            if (l < nt && sl >= 0 && sl < bz) {
-                const int o = gofs(jz0 + sl - t0 - l, h_xy[i]);  // z = jz - d
+            const int l = h_l[i];
+            if (l < nt && (uint32_t)(s - l) < (uint32_t)bz) {
+                const bool ok = (uint32_t)(s - h_zlo[i]) < (uint32_t)nz;
+                const int o = ok ? (int)(h_off[i] + (uint32_t)s * PB) : OOB;
                 const bool ev = (l & 1) == 0;
                 const A a = IO<S>::ld(rhE, ev ? o : OOB), b = IO<S>::ld(rhO, ev ? OOB : o);
                 hv[i] = ev ? a : b;
@@ -143,10 +156,10 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
 #pragma unroll
         for (int i = 0; i < HPF; ++i) {
             const int l = h_l[i], sl = s - l;
-            if (l < nt && sl >= 0 && sl < bz) (&ring(l + 1, jz0 + sl, 0, 0))[h_lds[i]] = hv[i];
+            if (l < nt && (uint32_t)sl < (uint32_t)bz) (&ring(l + 1, jz0 + sl, 0, 0))[h_lds[i]] = hv[i];
         }
     };
-    pf0_load(jz0 + 1);
+    pf0_load(-1);  // plane jz0 + 1
     halo_load(0);
     __syncthreads();
 
@@ -159,7 +172,7 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
         pf0_store(jz0 + s + 1);
         halo_store(s);
         __syncthreads();
-        pf0_load(jz0 + s + 2);
+        pf0_load(s);
         halo_load(s + 1);
         for (int l = 0; l < nt; ++l) {
             const int jz = jz0 + s - l;
@@ -222,8 +235,8 @@ bool tiled3d_supported(const int* b) {
     if (b[3] != 64) return false;
     if (b[2] != 2 && b[2] != 4 && b[2] != 8) return false;
     if (b[1] < 2 || b[0] < 1 || b[0] > 16) return false;
-    // halo prefetch slots: HPF * threads >= bt * (2*66 + 2*by)
-    if (8 * 64 * b[2] < b[0] * (2 * 66 + 2 * b[2])) return false;
+    // halo prefetch slots: HPF * threads >= bt * (2*66 + 2*by), HPF = 4 (by = 8) or 8
+    if ((b[2] == 8 ? 4 : 8) * 64 * b[2] < b[0] * (2 * 66 + 2 * b[2])) return false;
     // ring-0 plane prefetch: 4 * threads >= (by+2) * 66
     if (4 * 64 * b[2] < (b[2] + 2) * 66) return false;
     const size_t lds = (size_t)(b[0] + 1) * 4 * (b[2] + 2) * 66 * 8;
