@@ -240,7 +240,7 @@ def workload_heat3d(args, pc, torch, dtype):
     import numpy as np
     import synth
     n, TT = 512, 128
-    tile = {"f64": (2, 32, 8, 64), "f32": (4, 32, 8, 64), "bf16": (4, 32, 8, 64)}[dtype]
+    tile = {"f64": (2, 64, 16, 64), "f32": (4, 32, 8, 64), "bf16": (4, 32, 8, 64)}[dtype]
     sched = "slt_wave"
     upd = (n - 2) ** 3 * TT
     u = synth.heat3d_input(n)

@@ -218,7 +218,7 @@ typedef struct {
 /* Candidate grid of a problem (host only):
  *   Jacobi-1D: b_t in {16,32,64,128,256} x b_x in {64,128,256}
  *   Jacobi-2D: b_t in {4,8,16,32,64} x b_y in {16,32,64,128,256} x b_x in {64,128,256}
- *   Heat-3D:   b_t in {2,4,8} x b_z in {16,64,256} x b_y in {2,4,8}, b_x = 64
+ *   Heat-3D:   b_t in {2,4,8} x b_z in {16,64,256} x b_y in {2,4,8,16}, b_x = 64
  *   DP:        b in {32,64} (s[0] = s[1]) x k-chunk in {32,64,128,256}
  * each crossed with the schedules of sched_mask (stencils: the four tiled
  * schedules; DP: SLT_WAVE and COT_PAR), keeping only runnable tiles.  Writes

@@ -121,12 +121,12 @@ pcot_status validate(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T
     return PCOT_OK;
 }
 
-bool tile_ok(int kind, const int* b) {
+bool tile_ok(int kind, int dtype, const int* b) {
     int bb[4] = {b[0], b[1], b[2], b[3]};
     switch (kind) {
         case PCOT_JACOBI1D_3PT: return tiled1d_supported(bb);
         case PCOT_JACOBI2D_5PT: return tiled2d_supported(bb);
-        default: return tiled3d_supported(bb);
+        default: return tiled3d_supported(bb, dtype == PCOT_F64 ? 8 : 4);
     }
 }
 
@@ -427,7 +427,7 @@ pcot_status batch_validate(int32_t kind, int32_t dtype, int32_t n, const int64_t
     for (int i = 0; i < n; ++i) {
         pcot_status st = validate(kind, dtype, dims + 3 * (size_t)i, T[i], tiles + i, schedule, B.p[i]);
         if (st != PCOT_OK) return fail(st, "instance %d: %s", i, g_err.c_str());
-        if (!tile_ok(kind, B.p[i].b)) return fail(PCOT_ERR_UNSUPPORTED, "instance %d: tile not runnable", i);
+        if (!tile_ok(kind, dtype, B.p[i].b)) return fail(PCOT_ERR_UNSUPPORTED, "instance %d: tile not runnable", i);
     }
     const Prob& p0 = B.p[0];
     const int d = p0.d;
@@ -438,7 +438,7 @@ pcot_status batch_validate(int32_t kind, int32_t dtype, int32_t n, const int64_t
         if (d == 3 && q.b[2] != p0.b[2]) return fail(PCOT_ERR_UNSUPPORTED, "instance %d: b_y differs within the batch", i);
         for (int j = 0; j < d; ++j) B.lb[j] = std::max(B.lb[j], q.b[j]);
     }
-    if (!tile_ok(kind, B.lb)) return fail(PCOT_ERR_UNSUPPORTED, "no executor instance covers the batch's largest tile");
+    if (!tile_ok(kind, dtype, B.lb)) return fail(PCOT_ERR_UNSUPPORTED, "no executor instance covers the batch's largest tile");
     return PCOT_OK;
 }
 
@@ -571,7 +571,7 @@ pcot_status pcot_stencil_tile_supported(int32_t kind, int32_t dtype, const pcot_
         if (tile->s[i] < 2) return fail(PCOT_ERR_INVALID, "tile.s[%d] < 2", i);
         b[i + 1] = tile->s[i];
     }
-    if (!tile_ok(kind, b)) return fail(PCOT_ERR_UNSUPPORTED, "tile (%d; %d,%d,%d) not runnable for kind %d", b[0], b[1], b[2], b[3], kind);
+    if (!tile_ok(kind, dtype, b)) return fail(PCOT_ERR_UNSUPPORTED, "tile (%d; %d,%d,%d) not runnable for kind %d dtype %d", b[0], b[1], b[2], b[3], kind, dtype);
     return PCOT_OK;
 }
 
@@ -602,7 +602,7 @@ pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, i
         const char* b = (const char*)out;
         if (a < b + bytes && b < a + bytes) return fail(PCOT_ERR_INVALID, "in and out overlap");
     }
-    if (schedule != PCOT_NAIVE && !tile_ok(kind, p.b))
+    if (schedule != PCOT_NAIVE && !tile_ok(kind, dtype, p.b))
         return fail(PCOT_ERR_UNSUPPORTED, "tile (%d; %d,%d,%d) not runnable for kind %d dtype %d", p.b[0], p.b[1],
                     p.b[2], p.b[3], kind, dtype);
     if (T == 0) {

@@ -81,7 +81,7 @@ bool tiled1d_supported(const int* b);
 hipError_t launch_tiled1d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
 bool tiled2d_supported(const int* b);
 hipError_t launch_tiled2d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
-bool tiled3d_supported(const int* b);
+bool tiled3d_supported(const int* b, int lds_elem);
 hipError_t launch_tiled3d(int dtype, const int* b, const TiledLaunch& L, int grid_cap, hipStream_t s);
 
 }  // namespace pcot

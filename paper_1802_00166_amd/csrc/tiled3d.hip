@@ -113,7 +113,7 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     // halo of plane jz of ring v (v >= 1): rows ry = 0, 1 (all RX columns) and
     // columns rx = 0, 1 of rows 2..RY-1: 2*RX + 2*by values per level
     constexpr int HL = 2 * RX + 2 * by;
-    constexpr int HPF = BY == 8 ? 4 : 8;  // halo slots per thread per step (all levels)
+    constexpr int HPF = BY == 16 ? 2 : (BY == 8 ? 4 : 8);  // halo slots per thread per step (all levels)
     A hv[HPF];
     // level (nt: idle), in-plane LDS index, first step with z >= 0 (far
     // below any step when the row lies outside the array), offset at step 0
@@ -224,22 +224,22 @@ hipError_t launch_dtype(const int* b, const TiledLaunch& Lc, hipStream_t s) {
         case 2: return launch_by<S, 2>(Lc, lds, s);
         case 4: return launch_by<S, 4>(Lc, lds, s);
         case 8: return launch_by<S, 8>(Lc, lds, s);
+        case 16: return launch_by<S, 16>(Lc, lds, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-bool tiled3d_supported(const int* b) {
-    // b = {bt, bz, by, bx}; LDS rings must fit (sized for the f64 case)
+bool tiled3d_supported(const int* b, int lds_elem) {
+    // b = {bt, bz, by, bx}; lds_elem: bytes of one ring value (8 for f64, 4 otherwise)
     if (b[3] != 64) return false;
-    if (b[2] != 2 && b[2] != 4 && b[2] != 8) return false;
+    if (b[2] != 2 && b[2] != 4 && b[2] != 8 && b[2] != 16) return false;
     if (b[1] < 2 || b[0] < 1 || b[0] > 16) return false;
-    // halo prefetch slots: HPF * threads >= bt * (2*66 + 2*by), HPF = 4 (by = 8) or 8
-    if ((b[2] == 8 ? 4 : 8) * 64 * b[2] < b[0] * (2 * 66 + 2 * b[2])) return false;
-    // ring-0 plane prefetch: 4 * threads >= (by+2) * 66
-    if (4 * 64 * b[2] < (b[2] + 2) * 66) return false;
-    const size_t lds = (size_t)(b[0] + 1) * 4 * (b[2] + 2) * 66 * 8;
+    // halo prefetch slots: HPF * threads >= bt * (2*66 + 2*by)
+    const int hpf = b[2] == 16 ? 2 : (b[2] == 8 ? 4 : 8);
+    if (hpf * 64 * b[2] < b[0] * (2 * 66 + 2 * b[2])) return false;
+    const size_t lds = (size_t)(b[0] + 1) * 4 * (b[2] + 2) * 66 * lds_elem;
     return lds <= 150 * 1024;
 }
 

@@ -85,7 +85,7 @@ std::vector<std::pair<pcot_tile, int32_t>> candidates(const pcot_problem* p, uin
         case PCOT_HEAT3D_7PT:
             for (int bt : {2, 4, 8})
                 for (int bz : {16, 64, 256})
-                    for (int by : {2, 4, 8}) tiles.push_back(mk(bt, bz, by, 64));
+                    for (int by : {2, 4, 8, 16}) tiles.push_back(mk(bt, bz, by, 64));
             break;
         case PCOT_MATRIX_CHAIN:
             for (int b : {32, 64})

@@ -84,6 +84,7 @@ def test_jacobi1d_eigenmode_on_gpu(gpu):
     ((12, 30, 40), 5, (2, 5, 8, 64)),
     ((24, 20, 100), 20, (8, 6, 4, 64)),   # rings beyond 64 KiB of LDS
     ((9, 9, 9), 7, (1, 2, 2, 64)),        # smallest leaf
+    ((20, 40, 70), 9, (2, 8, 16, 64)),    # 16 waves per leaf
 ])
 def test_heat3d_f64_all_schedules_bit_exact(gpu, shape, T, tile, sched):
     u0 = field("heat3d", shape, "f64", 21)
@@ -99,6 +100,15 @@ def test_heat3d_f32_bf16_bit_exact(gpu, sched, dtype):
     want = oracle.stencil("heat3d", dtype, u0, 12)
     got = run("heat3d", dtype, u0, 12, (4, 16, 4, 64), sched)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_heat3d_wide_leaves_f32_bf16_bit_exact(gpu, dtype):
+    """b_y = 16 and b_t = 8 leaves, whose rings fit LDS only for 4-byte values."""
+    u0 = field("heat3d", (26, 50, 90), dtype, 24)
+    want = oracle.stencil("heat3d", dtype, u0, 13)
+    for tile in [(4, 16, 16, 64), (8, 8, 8, 64)]:
+        assert np.array_equal(run("heat3d", dtype, u0, 13, tile, "slt_wave"), want), tile
 
 
 def test_heat3d_tiny_fields_and_small_T(gpu):
