@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 NY = NX = 4096
 T = 512
 UPDATES = (NY - 2) * (NX - 2) * T
-DEFAULT_TILE = (32, 64, 256)
+DEFAULT_TILE = (16, 64, 256)
 DEFAULT_SCHED = "slt_wave"
 
 HBM_PEAK_GBS = 8000.0
@@ -401,6 +401,44 @@ def workload_batched(args, pc, torch):
     return rec
 
 
+def workload_tile_variability(args, pc, torch):
+    """Run-time spread over the tile space of the Jacobi-2D headline problem,
+    per schedule: every feasible candidate of the tuner's grid (b_t, b_y, b_x)
+    timed under SLT_LEX, SLT_WAVE, COT_SEQ and COT_PAR (median of `steps`
+    runs after one warm-up each).  The paper's robustness claim is about this
+    spread (how much the choice of tile sizes matters under each schedule), so
+    the record carries mean, standard deviation and relative standard
+    deviation of the times; the value is the best candidate's rate."""
+    import numpy as np
+    from paper_1802_00166_amd import tune
+    prob = tune.problem("jacobi2d", "f64", (NY, NX), T)
+    per, best = {}, None
+    for sch in ["slt_lex", "slt_wave", "cot_seq", "cot_par"]:
+        t0 = time.perf_counter()
+        _, _, _, recs = tune.sweep(prob, reps=max(3, args.steps // 2), warmup=1, schedules=[sch])
+        ms = np.array([r["ms"] for r in recs])
+        g = UPDATES / (ms * 1e-3) / 1e9
+        b = int(np.argmin(ms))
+        per[sch] = {"candidates": int(len(ms)), "best_tile": list(recs[b]["tile"]), "best_ms": round(float(ms[b]), 4),
+                    "best_gupd_s": round(float(g[b]), 2), "median_ms": round(float(np.median(ms)), 4),
+                    "mean_ms": round(float(ms.mean()), 4), "std_ms": round(float(ms.std()), 4),
+                    "rsd": round(float(ms.std() / ms.mean()), 4), "worst_over_best": round(float(ms.max() / ms[b]), 3),
+                    "mean_gupd_s": round(float(g.mean()), 2), "sweep_s": round(time.perf_counter() - t0, 1)}
+        print("# %s: %d candidates, best %s %.3f ms, RSD %.3f" % (sch, len(ms), per[sch]["best_tile"], ms[b],
+                                                                  per[sch]["rsd"]), file=sys.stderr, flush=True)
+        if best is None or ms[b] < best[2]:
+            best = (sch, tuple(recs[b]["tile"]), float(ms[b]))
+    sch, tile, bms = best
+    rec = _record("GUpdates/s, Jacobi-2D 4096^2 FP64, T=512: best of the full tile sweep; run-time spread per schedule",
+                  UPDATES / (bms * 1e-3) / 1e9, "GUpdates/s", max(3, args.steps // 2), 1, bms * 1e-3, "f64",
+                  "synthetic: sin(pi x)sin(pi y) + 1e-3*(2U-1) noise (SplitMix64 stream 2), zero boundary",
+                  {"workload": "jacobi2d_5pt_4096x4096_T512_f64_tile_sweep", "tile_bt_by_bx": list(tile),
+                   "schedule": sch},
+                  _roof(UPDATES, bms * 1e-3, 8 * (2.0 / tile[0] + 4.0 / tile[1] + 4.0 / tile[2]), 5), None)
+    rec["variability"] = per
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -414,7 +452,7 @@ def main():
                     help="only run the plain copy used to scale the HBM traffic counters")
     ap.add_argument("--workload", default="jacobi2d",
                     choices=["jacobi2d", "jacobi1d", "heat3d_f64", "heat3d_f32", "heat3d_bf16", "matrix_chain",
-                             "batched"])
+                             "batched", "tile_variability"])
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
@@ -432,6 +470,8 @@ def main():
             rec = workload_heat3d(args, pc, torch, args.workload.split("_")[1])
         elif args.workload == "matrix_chain":
             rec = workload_matrix_chain(args, pc, torch)
+        elif args.workload == "tile_variability":
+            rec = workload_tile_variability(args, pc, torch)
         else:
             rec = workload_batched(args, pc, torch)
         print(json.dumps(rec), flush=True)

@@ -61,7 +61,9 @@ template <int C> __device__ __forceinline__ int rpos_m1(int lane) {
 }
 
 template <typename A, int C, int G> struct Smem {
-    A hand[G][2][2][Cfg<C, G>::ROW];   // [g]: input rows of wave g (g > 0); parity by step, row of pair
+    // [g]: input rows of wave g (g > 0); parity by step, row of pair (two
+    // rows per step only when a lane holds at most two columns)
+    A hand[G][2][C <= 2 ? 2 : 1][Cfg<C, G>::ROW];
     A bchunk[2][Cfg<C, G>::KB][Cfg<C, G>::ROW];
     A lfs[G][128];                     // left faces of the current chunk, per wave
     A rfs[G][128];                     // right faces of the current chunk, per wave
@@ -328,22 +330,37 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
         return IO<S>::ld(r, offs(y, x));
     };
 
-    A in1[L][C], in2[L][C], x1a[L], x1b[L], x2a[L];
-    // history before the first row: input rows jy0-1 and jy0-2 of every level;
-    // level t's input row jy' holds u_t[jy' - t + 1][jx - t + 1]
+    // Input rows of every level in three register banks used in rotation:
+    // at step S_ bank S_ % 3 receives the new row, bank (S_ + 2) % 3 holds the
+    // row before it and bank (S_ + 1) % 3 the one before that, so rows move on
+    // without register copies (the step loop is unrolled by three).  Per bank:
+    // the lane's C columns, and the values at jx-1 and jx-2 (lane-1's last
+    // two columns, or the left faces for lane 0).
+    A H[L][3][C], XA[L][3], XB[L][3];
+    // history before the first row (step w): input rows jy0-1 and jy0-2 of
+    // every level; level t's input row jy' holds u_t[jy' - t + 1][jx - t + 1]
+    auto load_hist = [&](auto b1c, auto b2c) {
+        constexpr int B1 = decltype(b1c)::value, B2 = decltype(b2c)::value;
 #pragma unroll
-    for (int l = 0; l < L; ++l) {
-        const int t = tl0 + l;
-        const uintptr_t ps = pick(pick(pb0, pb1, t), pin, t == 0);
-        const rsrc_t rs = make_rsrc(uptr((const void*)ps), bytes);
-        const int y1 = jy0 - t, y2 = jy0 - t - 1, x = jxl - t;
-        x1b[l] = ldv(rs, y1, x - 1);
-        x1a[l] = ldv(rs, y1, x);
+        for (int l = 0; l < L; ++l) {
+            const int t = tl0 + l;
+            const uintptr_t ps = pick(pick(pb0, pb1, t), pin, t == 0);
+            const rsrc_t rs = make_rsrc(uptr((const void*)ps), bytes);
+            const int y1 = jy0 - t, y2 = jy0 - t - 1, x = jxl - t;
+            XB[l][B1] = ldv(rs, y1, x - 1);
+            XA[l][B1] = ldv(rs, y1, x);
 #pragma unroll
-        for (int c = 0; c < C; ++c) in1[l][c] = ldv(rs, y1, x + 1 + c);
-        x2a[l] = ldv(rs, y2, x);
+            for (int c = 0; c < C; ++c) H[l][B1][c] = ldv(rs, y1, x + 1 + c);
+            XA[l][B2] = ldv(rs, y2, x);
+            XB[l][B2] = A(0);  // never read: jx-2 is used only from the previous row
 #pragma unroll
-        for (int c = 0; c < C; ++c) in2[l][c] = ldv(rs, y2, x + 1 + c);
+            for (int c = 0; c < C; ++c) H[l][B2][c] = ldv(rs, y2, x + 1 + c);
+        }
+    };
+    switch (w % 3) {  // the first row of wave w is computed at step w
+        case 0: load_hist(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{}); break;
+        case 1: load_hist(std::integral_constant<int, 0>{}, std::integral_constant<int, 2>{}); break;
+        default: load_hist(std::integral_constant<int, 1>{}, std::integral_constant<int, 0>{}); break;
     }
     unsigned colok = 0xFFFFFFFFu;  // BND: bit l*C+c = column c of level l is interior
     if (BND) {
@@ -402,18 +419,19 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
     A* const rf_base = lane == 63 ? &sm.rfs[w][0] : &sm.junk[w][2 * lane];
     const int rf_stride = lane == 63 ? 2 : 0;
 
-    // all levels of one row step; TAIL: one of the tile's two last rows, where
-    // every level also writes its row (the two-wide high face)
-    auto levels = [&](auto tail, int S_, int r, int rk) {
+    // all levels of one row step at step phase PH = S_ % 3; TAIL: one of the
+    // tile's two last rows, where every level also writes its row (the
+    // two-wide high face)
+    auto levels = [&](auto tail, auto ph, int S_, int r, int rk) {
         constexpr bool TAIL = decltype(tail)::value;
+        constexpr int P0 = decltype(ph)::value, P1 = (P0 + 2) % 3, P2 = (P0 + 1) % 3;  // new, previous, before
         const int jy = jy0 + r;
-        A in0[C], x0a, x0b;
         {
             const A* h = w == 0 ? &sm.bchunk[(r / KB) & 1][r % KB][0] : &sm.hand[w][(S_ - 1) & 1][0][0];
-            x0b = h[rpos_m2<C>(lane)];
-            x0a = h[rpos_m1<C>(lane)];
+            XB[0][P0] = h[rpos_m2<C>(lane)];
+            XA[0][P0] = h[rpos_m1<C>(lane)];
 #pragma unroll
-            for (int c = 0; c < C; ++c) in0[c] = h[2 + c * 64 + lane];
+            for (int c = 0; c < C; ++c) H[0][P0][c] = h[2 + c * 64 + lane];
         }
         // left faces of every level for this row, read before any LDS write of
         // the step so that they are off the level-to-level dependency chain
@@ -431,23 +449,15 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
             A out[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const A cc = c >= 1 ? in1[l][c - 1] : x1a[l];
-                const A nn = c >= 1 ? in2[l][c - 1] : x2a[l];
-                const A ss = c >= 1 ? in0[c - 1] : x0a;
-                const A ee = in1[l][c];
-                const A ww = c >= 2 ? in1[l][c - 2] : (c == 1 ? x1a[l] : x1b[l]);
+                const A cc = c >= 1 ? H[l][P1][c - 1] : XA[l][P1];
+                const A nn = c >= 1 ? H[l][P2][c - 1] : XA[l][P2];
+                const A ss = c >= 1 ? H[l][P0][c - 1] : XA[l][P0];
+                const A ee = H[l][P1][c];
+                const A ww = c >= 2 ? H[l][P1][c - 2] : (c == 1 ? XA[l][P1] : XB[l][P1]);
                 A v = Tr<S>::rnd(jac2(cc, nn, ss, ee, ww));
                 if (BND) v = (rok && ((colok >> (l * C + c)) & 1u)) ? v : cc;
                 out[c] = v;
             }
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                in2[l][c] = in1[l][c];
-                in1[l][c] = in0[c];
-            }
-            x2a[l] = x1a[l];
-            x1a[l] = x0a;
-            x1b[l] = x0b;
             const rsrc_t rd = (l & 1) ? rdO : rdE;
             auto store_row = [&]() {
 #pragma unroll
@@ -456,29 +466,30 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
                     IO<S>::st(rd, BND ? ((rok && ((colok >> (l * C + c)) & 1u)) ? offs(y, x) : OOB) : offs(y, x), out[c]);
                 }
             };
-            auto pass_on = [&]() {
-                const A lfA = lfa[l], lfB = lfb[l];
-                x0a = shr1(out[C - 1], lfA);
-                if constexpr (C >= 2) x0b = shr1(out[C >= 2 ? C - 2 : 0], lfB);
-                else x0b = shr1(x0a, lfB);
+            // out is the next level's new input row: its values at jx-1 and
+            // jx-2 come from lane-1 (left faces for lane 0)
+            auto pass_on = [&](A& xa, A& xb) {
+                xa = shr1(out[C - 1], lfa[l]);
+                if constexpr (C >= 2) xb = shr1(out[C >= 2 ? C - 2 : 0], lfb[l]);
+                else xb = shr1(xa, lfb[l]);
                 A* rf = rf_base + rf_stride * (rk * L + l);
-                rf[0] = C >= 2 ? out[C >= 2 ? C - 2 : 0] : x0a;
+                rf[0] = C >= 2 ? out[C >= 2 ? C - 2 : 0] : xa;
                 rf[1] = out[C - 1];
                 if (TAIL) store_row();
-#pragma unroll
-                for (int c = 0; c < C; ++c) in0[c] = out[c];
-                return std::pair<A, A>(lfA, lfB);
             };
             if (l + 1 < L) {
-                pass_on();
+                pass_on(XA[l + 1 < L ? l + 1 : 0][P0], XB[l + 1 < L ? l + 1 : 0][P0]);
+#pragma unroll
+                for (int c = 0; c < C; ++c) H[l + 1 < L ? l + 1 : 0][P0][c] = out[c];
             } else if (!topwave) {
-                const auto lf = pass_on();
+                A xa, xb;
+                pass_on(xa, xb);
                 A* h = &sm.hand[w + 1 < G ? w + 1 : 0][S_ & 1][0][0];
 #pragma unroll
                 for (int c = 0; c < C; ++c) h[2 + c * 64 + lane] = out[c];
                 if (lane == 0) {
-                    h[0] = lf.second;
-                    h[1] = lf.first;
+                    h[0] = lfb[l];
+                    h[1] = lfa[l];
                 }
             } else {
                 store_row();  // top plane
@@ -492,7 +503,7 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
     chunk_fetch(1);
     __syncthreads();
     const int nsteps = by + G - 1;
-    for (int S_ = 0; S_ < nsteps; ++S_) {
+    auto step = [&](auto ph, int S_) {
         if (S_ % KB == 0 && S_ > 0) {
             // publish chunk c = S_/KB (loaded during chunk c-1) before any
             // store of this step, then start loading chunk c+1
@@ -509,8 +520,8 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
                 __builtin_amdgcn_wave_barrier();
                 lf_fetch(r + K);
             }
-            if (r < by - 2) levels(std::integral_constant<bool, false>{}, S_, r, rk);
-            else levels(std::integral_constant<bool, true>{}, S_, r, rk);
+            if (r < by - 2) levels(std::integral_constant<bool, false>{}, ph, S_, r, rk);
+            else levels(std::integral_constant<bool, true>{}, ph, S_, r, rk);
             if (rk == K - 1 || r == by - 1) {
                 // flush the staged right faces of this chunk: lane i -> (row, level)
                 __builtin_amdgcn_wave_barrier();
@@ -528,6 +539,11 @@ __device__ __forceinline__ void exec_full(const TiledProblem& P, int kt, int ky,
             }
         }
         __syncthreads();
+    };
+    for (int S0 = 0; S0 < nsteps; S0 += 3) {
+        step(std::integral_constant<int, 0>{}, S0);
+        if (S0 + 1 < nsteps) step(std::integral_constant<int, 1>{}, S0 + 1);
+        if (S0 + 2 < nsteps) step(std::integral_constant<int, 2>{}, S0 + 2);
     }
 }
 
@@ -838,10 +854,12 @@ hipError_t launch_dtype(const int* b, const TiledLaunch& Lc, hipStream_t s) {
     const int bt = b[0];
 #define PCOT_TL(CC, LL, GG) \
     if (C == CC && bt <= LL * GG) return launch_inst<S, CC, LL, GG>(Lc, s);
-    // levels per wave: 8 for 1-2 columns per lane, 4 for 4 (register budget)
+    // levels per wave: 8 for 1-2 columns per lane, 4 for 4 (register budget);
+    // for 4 columns and b_t in (8, 16], 8 waves of 2 levels (measured faster
+    // than 4 waves of 4: a shorter level chain per step)
     PCOT_TL(1, 4, 1) PCOT_TL(1, 8, 1) PCOT_TL(1, 8, 2) PCOT_TL(1, 8, 4) PCOT_TL(1, 8, 8)
     PCOT_TL(2, 4, 1) PCOT_TL(2, 8, 1) PCOT_TL(2, 8, 2) PCOT_TL(2, 8, 4) PCOT_TL(2, 8, 8)
-    PCOT_TL(4, 4, 1) PCOT_TL(4, 4, 2) PCOT_TL(4, 4, 4) PCOT_TL(4, 4, 8)
+    PCOT_TL(4, 4, 1) PCOT_TL(4, 4, 2) PCOT_TL(4, 2, 8) PCOT_TL(4, 4, 8)
 #undef PCOT_TL
     return hipErrorInvalidValue;
 }
