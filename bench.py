@@ -103,6 +103,25 @@ def calibrate_copy(reps=5):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": reps}), flush=True)
 
 
+def measure_copy_gbs(torch, reps=5):
+    """Achieved bandwidth of a plain 1 GiB device-to-device copy (read +
+    written bytes over HIP-event time): the practical ceiling the executor's
+    HBM rate is also compared with."""
+    n = 128 << 20
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(u0, sample_T=T):
     """Oracle on the host: the full 4096^2 field for `sample_T` steps (by
     default the whole job), on up to 16 host threads (the threaded oracle
@@ -530,6 +549,11 @@ def main():
         "tiles": tiles,
     }
     if not args.no_cpu:
+        cg = measure_copy_gbs(torch)
+        r = rec["roofline"]
+        r["copy_gbs"] = round(cg, 1)
+        if r.get("unit") == "GB/s":
+            r["frac_of_copy"] = round(r["achieved"] / cg, 4)
         rec["cpu_baseline"] = cpu_baseline(u0)
     print(json.dumps(rec), flush=True)
 
