@@ -21,11 +21,13 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace pcot {
 
 namespace {
 
-template <typename S, int BY>
+template <typename S, int BY, bool BND>
 __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, typename Tr<S>::A* lds) {
     using A = typename Tr<S>::A;
     constexpr int ES = sizeof(S);
@@ -50,9 +52,14 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
         return z >= 1 && z <= nz - 2 && y >= 1 && y <= ny - 2 && x >= 1 && x <= nx - 2;
     };
     auto offs = [&](int z, int y, int x) { return ((z * ny + y) * nx + x) * ES; };
-    // ring v (v = 0: u_t0; v = l+1: outputs of level t0+l), plane jz, ring row/col
+    // ring v (v = 0: u_t0; v = l+1: outputs of level t0+l), plane jz, ring
+    // row/col.  A plane's slot is the step that writes it, mod 4 (level l
+    // writes plane jz0 + s - l of ring l+1 at step s; ring 0's plane jz0+s+1
+    // is published at step s), so at step s every level reads slots s-1, s-2,
+    // s-3 and writes slot s: with the step loop unrolled by four, all ring
+    // addresses of a level are one base plus constants.
     auto ring = [&](int v, int jz, int ry, int rx) -> A& {
-        return lds[((v * 4 + ((jz - jz0 + 4) & 3)) * RY + ry) * RX + rx];
+        return lds[((v * 4 + ((jz - jz0 + v + 3) & 3)) * RY + ry) * RX + rx];
     };
     // ring v's value at skewed (jz, jy, jx): u_{t0+v} at the point
     // (jz, jy, jx) - (t0+v-1), read from global; v must be wave-uniform
@@ -165,8 +172,12 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
 
     const int jy = jy0 + w, jx = jx0 + lane;
     const int ry = w + 2, rx = lane + 2;
+    const int tc = (ry - 1) * RX + (rx - 1);  // the thread's centre input within a plane
     const int nsteps = bz + nt - 1;
-    for (int s = 0; s < nsteps; ++s) {
+    auto step = [&](auto qc, int s) {
+        // slots of this step (s % 4 = Q): written, z+ plane, centre plane, z- plane
+        constexpr int Q = decltype(qc)::value;
+        constexpr int SW = Q, SP = (Q + 3) & 3, SC = (Q + 2) & 3, SM = (Q + 1) & 3;
         // publish the prefetched ring-0 plane jz0+s+1 and the halos of this
         // step's output planes, then start the next prefetches
         pf0_store(jz0 + s + 1);
@@ -178,19 +189,25 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
             const int jz = jz0 + s - l;
             if (jz < jz0 || jz >= jz0 + bz) continue;  // uniform
             const int t = t0 + l;
-            const A u = ring(l, jz - 1, ry - 1, rx - 1);
-            const A v = Tr<S>::rnd(heat3(u, ring(l, jz - 1, ry - 1, rx), ring(l, jz - 1, ry - 1, rx - 2),
-                                         ring(l, jz - 1, ry, rx - 1), ring(l, jz - 1, ry - 2, rx - 1),
-                                         ring(l, jz, ry - 1, rx - 1), ring(l, jz - 2, ry - 1, rx - 1)));
+            const A* rl = lds + l * (4 * PL) + tc;  // ring l around the centre input
+            const A u = rl[SC * PL];
+            const A v = Tr<S>::rnd(heat3(u, rl[SC * PL + 1], rl[SC * PL - 1], rl[SC * PL + RX], rl[SC * PL - RX],
+                                         rl[SP * PL], rl[SM * PL]));
             const int z = jz - t, y = jy - t, x = jx - t;
-            const bool in = inside(z, y, x);
+            const bool in = !BND || inside(z, y, x);
             const A out = in ? v : u;
-            ring(l + 1, jz, ry, rx) = out;
+            lds[(l + 1) * (4 * PL) + SW * PL + ry * RX + rx] = out;
             const bool face = t == ttop || lane >= BX - 2 || w >= by - 2 || jz >= jz0 + bz - 2;
             // level l writes u_{t0+l+1}: the buffers of rings l+1 (hoisted descriptors)
             if (face && in) IO<S>::st((l & 1) ? rhO : rhE, offs(z, y, x), out);
         }
         __syncthreads();
+    };
+    for (int s0 = 0; s0 < nsteps; s0 += 4) {
+        step(std::integral_constant<int, 0>{}, s0);
+        if (s0 + 1 < nsteps) step(std::integral_constant<int, 1>{}, s0 + 1);
+        if (s0 + 2 < nsteps) step(std::integral_constant<int, 2>{}, s0 + 2);
+        if (s0 + 3 < nsteps) step(std::integral_constant<int, 3>{}, s0 + 3);
     }
 }
 
@@ -200,7 +217,11 @@ __global__ void __launch_bounds__(64 * BY) k_tiled3d(TiledLaunch Lc) {
     using A = typename Tr<S>::A;
     __shared__ int s_tk, s_go;
     run_queued_tile<3, true>(Lc, &s_tk, &s_go, [&](const TiledProblem& P, const int* k) {
-        exec3d<S, BY>(P, k, reinterpret_cast<A*>(smem_raw));
+        // tiles whose every point lies inside the array skip the per-point test
+        if (tile_interior<3>(P, k))
+            exec3d<S, BY, false>(P, k, reinterpret_cast<A*>(smem_raw));
+        else
+            exec3d<S, BY, true>(P, k, reinterpret_cast<A*>(smem_raw));
     });
 }
 
