@@ -45,11 +45,19 @@ template <> struct DV<unsigned> {
     static __device__ __forceinline__ unsigned madw(unsigned w, unsigned pk, unsigned a) {
         return __umul24(w, pk) + a;  // w, pk < 2^24: one v_mad_u32_u24
     }
+    static __device__ __forceinline__ unsigned add(unsigned a, unsigned b) { return a + b; }
     static __device__ __forceinline__ void amin(unsigned* p, unsigned v) { atomicMin(p, v); }
 };
 template <> struct DV<long long> {
     static constexpr long long INF = 0x7FFFFFFFFFFFFFFFLL;
-    static __device__ __forceinline__ long long madw(long long w, long long pk, long long a) { return w * pk + a; }
+    // wrapping arithmetic: exact for every candidate that can win (they are
+    // below 2^62); discarded slots may hold INF operands
+    static __device__ __forceinline__ long long madw(long long w, long long pk, long long a) {
+        return (long long)((unsigned long long)w * (unsigned long long)pk + (unsigned long long)a);
+    }
+    static __device__ __forceinline__ long long add(long long a, long long b) {
+        return (long long)((unsigned long long)a + (unsigned long long)b);
+    }
     static __device__ __forceinline__ void amin(long long* p, long long v) { atomicMin(p, v); }
 };
 
@@ -156,7 +164,8 @@ __global__ void __launch_bounds__(256) k_dp_fin(DPLaunch a) {
     __shared__ V T[B][B + 1];     // tile (I, J)
     __shared__ V DI[B][B + 1];    // tile (I, I) (unused when I == J)
     __shared__ V DJ[B][B + 1];    // tile (J, J) (unused when I == J)
-    __shared__ V red[256];
+    __shared__ V PA[B + 1];  // p[I*B .. I*B + B]: p[i] of the tile's rows, p[k+1] for k in block I
+    __shared__ V PB[B];      // p[J*B + 1 .. J*B + B]: p[j+1] of its columns, p[k+1] for k in block J
     const int2 tj = a.tiles[blockIdx.x];
     const int I = tj.x, J = tj.y;
     const int N = a.N;
@@ -171,16 +180,14 @@ __global__ void __launch_bounds__(256) k_dp_fin(DPLaunch a) {
             DJ[r][c] = Cw[(size_t)(J * B + r) * N + J * B + c];
         }
     }
+    if (tid <= B) PA[tid] = (V)a.p[I * B + tid];
+    if (tid < B) PB[tid] = (V)a.p[J * B + tid + 1];
     __syncthreads();
-    // operand lookups in global cell coordinates
-    auto at = [&](int gi, int gk) -> V {  // C[gi][gk]
-        const int bi = gi / B, bk = gk / B;
-        const int li = gi - bi * B, lk = gk - bk * B;
-        if (diag) return T[li][lk];
-        if (bi == I && bk == I) return DI[li][lk];
-        if (bi == J && bk == J) return DJ[li][lk];
-        return T[li][lk];  // (I, J)
-    };
+    // The row operand C[i][k] of a split k in block I lies in tile (I, I) (the
+    // tile itself when diagonal); its column operand C[k+1][j] in the tile.
+    // For k in block J the row operand is in the tile and the column operand
+    // in tile (J, J).
+    const V(*RA)[B + 1] = diag ? T : DI;
     const int cell = tid / TPC, part = tid % TPC;
     for (int s = 0; s <= 2 * B - 2; ++s) {
         // cell index along the anti-diagonal: u from max(0, s-B+1)
@@ -188,29 +195,43 @@ __global__ void __launch_bounds__(256) k_dp_fin(DPLaunch a) {
         const int v = s - u;
         const bool act = u < B && v >= 0 && v < B && u <= s;
         V best = DV<V>::INF;
-        int i = 0, j = 0;
+        int li = 0, lj = 0;
+        bool live = false;
         if (act) {
-            i = (I + 1) * B - 1 - u;
-            j = J * B + v;
-            if (i < j) {
-                const V wij = (V)a.p[i];
-                const V wj = (V)a.p[j + 1];
-                const int kA0 = i, kA1 = diag ? j : (I + 1) * B - 1;  // [kA0, kA1)
-                const int kB0 = diag ? j : J * B, kB1 = j;            // [kB0, kB1)
-                const int n1 = kA1 - kA0, n = n1 + (kB1 - kB0);
-                for (int q = part; q < n; q += TPC) {
-                    const int k = q < n1 ? kA0 + q : kB0 + (q - n1);
-                    const V cand = at(i, k) + at(k + 1, j) + wij * (V)a.p[k + 1] * wj;
-                    best = cand < best ? cand : best;
+            li = B - 1 - u;  // i = I*B + li
+            lj = v;          // j = J*B + lj
+            live = diag ? li < lj : true;
+            if (live) {
+                const V w = PA[li] * PB[lj];  // p[i] * p[j+1]
+                // block I: local k in [li, kA1); block J: local k in [0, lj)
+                const int kA1 = diag ? lj : B - 1;
+                const int n1 = kA1 - li, n = n1 + (diag ? 0 : lj);
+                // a fixed, unrolled number of slots per thread (at most 2B - 2
+                // splits per cell), so that all LDS reads of a step are in
+                // flight together; a slot past n reads a valid cell and is
+                // discarded
+#pragma unroll
+                for (int it = 0; it < (2 * B + TPC - 1) / TPC; ++it) {
+                    const int q = part + it * TPC;
+                    const bool inA = q < n1;
+                    const int ka = min(li + q, B - 2), kb = max(min(q - n1, B - 2), 0);
+                    const V* rop = inA ? &RA[li][ka] : &T[li][kb];
+                    const V* cop = inA ? &T[ka + 1][lj] : &DJ[kb + 1][lj];
+                    const V pk = inA ? PA[ka + 1] : PB[kb];
+                    const V cand = DV<V>::add(DV<V>::madw(w, pk, *rop), *cop);
+                    best = (q < n && cand < best) ? cand : best;
                 }
             }
         }
-        red[tid] = best;
-        __syncthreads();
-        if (act && part == 0 && i < j) {
-            V mm = T[i - I * B][j - J * B];  // external minimum (INF on diagonal tiles)
-            for (int q = 0; q < TPC; ++q) mm = red[tid + q] < mm ? red[tid + q] : mm;
-            T[i - I * B][j - J * B] = mm;
+        // min over the cell's TPC threads (adjacent lanes of one wave)
+#pragma unroll
+        for (int o = 1; o < TPC; o <<= 1) {
+            const V other = __shfl_xor(best, o, TPC);
+            best = other < best ? other : best;
+        }
+        if (act && part == 0 && live) {
+            const V mm = T[li][lj];  // external minimum (INF on diagonal tiles)
+            T[li][lj] = best < mm ? best : mm;
         }
         __syncthreads();
     }
