@@ -32,6 +32,8 @@ T = 512
 UPDATES = (NY - 2) * (NX - 2) * T
 DEFAULT_TILE = (16, 64, 256)
 DEFAULT_SCHED = "slt_wave"
+# Heat-3D 512^3, T = 128: the tile each storage type is benchmarked with
+HEAT3D_TILES = {"f64": (2, 64, 16, 64), "f32": (4, 32, 8, 64), "bf16": (4, 32, 8, 64)}
 
 HBM_PEAK_GBS = 8000.0
 # FP64 vector: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 non-fused FP64 ops/s
@@ -259,7 +261,7 @@ def workload_heat3d(args, pc, torch, dtype):
     import numpy as np
     import synth
     n, TT = 512, 128
-    tile = {"f64": (2, 64, 16, 64), "f32": (4, 32, 8, 64), "bf16": (4, 32, 8, 64)}[dtype]
+    tile = HEAT3D_TILES[dtype]
     sched = "slt_wave"
     upd = (n - 2) ** 3 * TT
     u = synth.heat3d_input(n)

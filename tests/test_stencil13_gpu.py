@@ -6,6 +6,8 @@ permutable nest and keeps each point's fixed operation order with no FMA
 contraction, so results must equal the oracle's bit for bit in every storage
 type.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -124,3 +126,19 @@ def test_heat3d_constant_field_fixed_on_gpu(gpu):
     """(c - 2c) + c = 0 exactly, so every constant field is a fixed point."""
     k = np.full((14, 12, 80), 0.3)
     assert np.array_equal(run("heat3d", "f64", k, 11, (4, 8, 4, 64), "slt_wave"), k)
+
+
+@pytest.mark.slow
+def test_heat3d_full_size_bench_tiles(gpu):
+    """Heat-3D 512^3, T = 128 in each storage type at the tile the benchmark
+    times: the whole field against the (threaded, bit-identical) oracle."""
+    import bench
+    threads = min(16, os.cpu_count() or 1)
+    u = synth.heat3d_input(512)
+    for dtype in ["f64", "f32", "bf16"]:
+        u0 = u if dtype == "f64" else (u.astype(np.float32) if dtype == "f32"
+                                       else synth.to_bf16_bits(u.astype(np.float32)))
+        want = oracle.stencil("heat3d", dtype, u0, 128, threads=threads)
+        got = run("heat3d", dtype, u0, 128, bench.HEAT3D_TILES[dtype], "slt_wave")
+        assert np.array_equal(got, want), dtype
+        del want, got
