@@ -32,6 +32,8 @@ T = 512
 UPDATES = (NY - 2) * (NX - 2) * T
 DEFAULT_TILE = (16, 64, 256)
 DEFAULT_SCHED = "slt_wave"
+# matrix chain N = 4096: (unused, b, b, k-chunk)
+CHAIN_TILE = (0, 32, 32, 64)
 # Heat-3D 512^3, T = 128: the tile each storage type is benchmarked with
 HEAT3D_TILES = {"f64": (2, 64, 16, 64), "f32": (4, 32, 8, 64), "bf16": (4, 32, 8, 64)}
 
@@ -316,7 +318,7 @@ def workload_heat3d(args, pc, torch, dtype):
 
 def workload_matrix_chain(args, pc, torch):
     import synth
-    N, pmax, tile, sched = 4096, 100, (0, 32, 32, 64), "slt_wave"
+    N, pmax, tile, sched = 4096, 100, CHAIN_TILE, "slt_wave"
     upd = (N ** 3 - N) // 6
     p = torch.from_numpy(synth.chain_dims(N)).to("cuda:0")
     C = torch.empty((N, N), dtype=torch.int64, device="cuda:0")
@@ -460,6 +462,74 @@ def workload_tile_variability(args, pc, torch):
     return rec
 
 
+# The paper's own problem shapes (its Table 2), deliberately not powers of
+# two: the Jacobi-2D rule at the Heat-2D shape, Heat-3D, and the interval DP
+# at N = 4000.  The paper's figures are single CPU cores running other code:
+# context, not a target.
+PAPER_SHAPES = {"jacobi2d": ((3000, 3000), 500), "heat3d": ((350, 350, 350), 50), "matrix_chain": 4000}
+PAPER_HEAT3D_TILE = (2, 64, 16, 64)
+
+
+def paper_jacobi2d_tile():
+    """The cost model's tile for the paper's Heat-2D shape (else the default)."""
+    try:
+        from paper_1802_00166_amd import tune
+        m = tune.load_default_model()
+        if m is not None:
+            (ny, nx), TT = PAPER_SHAPES["jacobi2d"]
+            return tune.predict_stencil(m, "jacobi2d", "f64", (ny, nx), TT, tune.MODEL_SCHEDULES)
+    except ImportError:
+        pass
+    return DEFAULT_TILE, DEFAULT_SCHED
+
+
+def workload_paper_shapes(args, pc, torch):
+    import numpy as np
+    import synth
+    rows = {}
+    (ny, nx), TT = PAPER_SHAPES["jacobi2d"]
+    tile, sched = paper_jacobi2d_tile()
+    u = synth.jacobi2d_input(ny, nx)
+    x = torch.from_numpy(u).to("cuda:0")
+    y = torch.empty_like(x)
+    ws = pc.alloc_workspace(pc.workspace_bytes("jacobi2d", "f64", (ny, nx), TT, tuple(tile), sched))
+    upd2 = (ny - 2) * (nx - 2) * TT
+    dt2, k2 = _timed(pc, torch, lambda: pc.stencil_run("jacobi2d", "f64", x, TT, tuple(tile), sched, out=y,
+                                                       workspace=ws), args.steps, args.warmup)
+    del x, y, ws
+    (nz, n1, n2), T3 = PAPER_SHAPES["heat3d"]
+    u3 = synth.heat3d_input(nz)
+    x = torch.from_numpy(u3).to("cuda:0")
+    y = torch.empty_like(x)
+    ws = pc.alloc_workspace(x.numel() * 8 + (64 << 20))
+    upd3 = (nz - 2) * (n1 - 2) * (n2 - 2) * T3
+    dt3, _ = _timed(pc, torch, lambda: pc.stencil_run("heat3d", "f64", x, T3, PAPER_HEAT3D_TILE, "slt_wave", out=y,
+                                                      workspace=ws), args.steps, args.warmup)
+    del x, y, ws
+    N = PAPER_SHAPES["matrix_chain"]
+    p = torch.from_numpy(synth.chain_dims(N)).to("cuda:0")
+    C = torch.empty((N, N), dtype=torch.int64, device="cuda:0")
+    ws = pc.alloc_workspace(pc.dp_workspace_bytes(N, CHAIN_TILE, "slt_wave"))
+    updc = (N ** 3 - N) // 6
+    dtc, _ = _timed(pc, torch, lambda: pc.dp_run(p, 100, CHAIN_TILE, "slt_wave", out=C, workspace=ws),
+                    args.steps, args.warmup)
+    rows["heat3d_7pt_350_T50_f64"] = {"gupd_s": round(upd3 / dt3 / 1e9, 2), "ms": round(dt3 * 1e3, 3),
+                                      "tile_bt_bz_by_bx": list(PAPER_HEAT3D_TILE), "schedule": "slt_wave",
+                                      "paper_cpu_1core_gupd_s": "about 1.1-1.2 (its Heat-3D, SLT sequential)"}
+    rows["matrix_chain_4000"] = {"gupd_s": round(updc / dtc / 1e9, 2), "ms": round(dtc * 1e3, 3),
+                                 "tile_b_b_kchunk": list(CHAIN_TILE[1:]), "schedule": "slt_wave",
+                                 "paper_cpu_1core_gupd_s": "21.0-22.8 (its OSP, SLT sequential)"}
+    rec = _record("GUpdates/s, Jacobi-2D 3000^2 FP64, T=500 (the paper's Heat-2D shape; learned tile)",
+                  upd2 / dt2 / 1e9, "GUpdates/s", args.steps, args.warmup, dt2, "f64",
+                  "synthetic: the headline's recipes at the paper's shapes (Jacobi-2D stream 2, Heat-3D stream 3, "
+                  "chain stream 5)",
+                  {"workload": "paper_shapes_jacobi2d_3000_T500_f64", "tile_bt_by_bx": list(tile), "schedule": sched},
+                  _roof(upd2, k2 / 1e3, alg_bytes_per_update(tuple(tile)), 5), None)
+    rec["paper_cpu_1core_gupd_s"] = "about 2.05 (its Heat-2D, SLT sequential; another update rule)"
+    rec["context_rows"] = rows
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -473,7 +543,7 @@ def main():
                     help="only run the plain copy used to scale the HBM traffic counters")
     ap.add_argument("--workload", default="jacobi2d",
                     choices=["jacobi2d", "jacobi1d", "heat3d_f64", "heat3d_f32", "heat3d_bf16", "matrix_chain",
-                             "batched", "tile_variability"])
+                             "batched", "tile_variability", "paper_shapes"])
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
@@ -493,6 +563,8 @@ def main():
             rec = workload_matrix_chain(args, pc, torch)
         elif args.workload == "tile_variability":
             rec = workload_tile_variability(args, pc, torch)
+        elif args.workload == "paper_shapes":
+            rec = workload_paper_shapes(args, pc, torch)
         else:
             rec = workload_batched(args, pc, torch)
         print(json.dumps(rec), flush=True)

@@ -84,8 +84,10 @@ def test_chain_errors(gpu):
 @pytest.mark.slow
 def test_chain_full_size(gpu):
     """N = 4096, p uniform in [1, 100]: whole triangle against the (threaded,
-    bit-identical) oracle, both schedules."""
+    bit-identical) oracle, at the benchmark's tile and under both schedules."""
     p = synth.chain_dims(4096)
     want = _upper(oracle.matrix_chain(p, threads=min(16, os.cpu_count() or 1)))
-    for tile, sched in [((0, 64, 64, 256), "slt_wave"), ((0, 64, 64, 256), "cot_par")]:
+    import bench
+    for tile, sched in [(bench.CHAIN_TILE, "slt_wave"), ((0, 64, 64, 256), "slt_wave"),
+                        ((0, 64, 64, 256), "cot_par")]:
         assert np.array_equal(_upper(_run(p, 100, tile, sched)), want), sched
