@@ -153,6 +153,33 @@ __global__ void __launch_bounds__(256) k_dp_ext(DPLaunch a) {
         for (int c = 0; c < R; ++c) DV<V>::amin(Cm + (size_t)(row0 + r) * N + col0 + c, m[r][c]);
 }
 
+// Minimum over groups of TPC adjacent lanes (TPC in {2, 4, 8}) with DPP lane
+// moves: swap neighbours, swap pairs within a quad, then mirror the two quads
+// of each half row (lane i of the 8 meets lane 7-i), so every lane ends with
+// the group's minimum.
+__device__ __forceinline__ unsigned dpp_move(unsigned v, int ctrl) {
+    switch (ctrl) {
+        case 0: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+        case 1: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+        default: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false); // row_half_mirror
+    }
+}
+__device__ __forceinline__ long long dpp_move(long long v, int ctrl) {
+    const unsigned lo = dpp_move((unsigned)(unsigned long long)v, ctrl);
+    const unsigned hi = dpp_move((unsigned)((unsigned long long)v >> 32), ctrl);
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+template <int TPC, typename V>
+__device__ __forceinline__ V group_min(V v) {
+    static_assert(TPC == 2 || TPC == 4 || TPC == 8, "group of 2, 4 or 8 lanes");
+#pragma unroll
+    for (int c = 0; (1 << c) < TPC; ++c) {
+        const V o = dpp_move(v, c);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
 // -------------------------------------------------------- finishing part ---
 // One block per tile.  Cells are taken by anti-diagonals of (u, v) =
 // ((I+1)B-1-i, j-JB): a cell's internal operands lie below it (same column)
@@ -224,11 +251,7 @@ __global__ void __launch_bounds__(256) k_dp_fin(DPLaunch a) {
             }
         }
         // min over the cell's TPC threads (adjacent lanes of one wave)
-#pragma unroll
-        for (int o = 1; o < TPC; o <<= 1) {
-            const V other = __shfl_xor(best, o, TPC);
-            best = other < best ? other : best;
-        }
+        best = group_min<TPC>(best);
         if (act && part == 0 && live) {
             const V mm = T[li][lj];  // external minimum (INF on diagonal tiles)
             T[li][lj] = best < mm ? best : mm;
