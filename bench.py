@@ -549,8 +549,8 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(multi-GPU sharding is described in DESIGN.md, not built)" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus %d is not supported "
+              "(sharding across GPUs is not implemented)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload != "jacobi2d":
         import torch

@@ -179,7 +179,7 @@ pcot_status pcot_dp_run(const int64_t* p, int64_t N, int64_t pmax, const pcot_ti
  * pcot_tune does the same on the GPU over the tile grids below, and a small
  * learned cost model, trained on such sweeps, predicts a good (tile,
  * schedule) without timing every candidate.  The sweep stays the reference
- * the model is judged against. */
+ * the model is measured against. */
 
 #define PCOT_MATRIX_CHAIN 4 /* pcot_problem.kind of the interval DP */
 
