@@ -145,6 +145,7 @@ def evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_st
     """Held-out evaluation: sweep, model pick re-timed, fixed tile."""
     two = ["slt_wave", "cot_par"]
     sweeps, evals = {}, []
+    held_sq = []  # squared ln-time prediction errors over every timed held-out candidate of the model's schedules
 
     def evaluate(kind, dtype, shape, T, schedules, fixed):
         prob = tune.problem(kind, dtype, shape, T)
@@ -158,6 +159,10 @@ def evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_st
         bt, bs, bms = tuple(best["tile"]), best["schedule"], best["ms"]
         sw_s = time.time() - t0
         mt, msch, pms = model.predict(prob, two)
+        mine = [r for r in recs if r["schedule"] in two]
+        if mine:
+            pred = model.predict_ms(mine)
+            held_sq.extend(float(np.log(pv) - np.log(r["ms"])) ** 2 for pv, r in zip(pred, mine))
         times = {(tuple(r["tile"]), r["schedule"]): r["ms"] for r in recs}
         # the pick and the fixed tile re-timed in one more session, beside the sweep's best
         t0 = time.time()
@@ -190,6 +195,8 @@ def evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_st
     rep = {
         "records": len(records), "train_shapes": len(train), "sweep_seconds": sweep_s, "train_seconds": train_s,
         "final_loss": getattr(model, "final_loss", None), "train_rmse_ln_ms": rmse,
+        "heldout_rmse_ln_ms": float(np.sqrt(np.mean(held_sq))) if held_sq else None,
+        "heldout_candidates": len(held_sq),
         "geomean_pick_over_best": float(math.exp(np.mean(np.log(ratios)))),
         "max_pick_over_best": float(max(ratios)),
         "geomean_gain_over_fixed": float(math.exp(np.mean(np.log(gains)))) if gains else None,
@@ -199,8 +206,9 @@ def evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_st
         json.dump(sweeps, f, indent=1)
     with open(os.path.join(args.out, "report.json"), "w") as f:
         json.dump(rep, f, indent=1)
-    log("geomean model/sweep %.4f (max %.4f), geomean gain over fixed tile %s" %
-        (rep["geomean_pick_over_best"], rep["max_pick_over_best"], rep["geomean_gain_over_fixed"]))
+    log("geomean model/sweep %.4f (max %.4f), geomean gain over fixed tile %s, held-out RMSE(ln ms) %s" %
+        (rep["geomean_pick_over_best"], rep["max_pick_over_best"], rep["geomean_gain_over_fixed"],
+         rep["heldout_rmse_ln_ms"]))
     return 0
 
 
