@@ -334,12 +334,29 @@ def workload_matrix_chain(args, pc, torch):
         c = time.perf_counter() - t0
         cpu = {"value": round((Ns ** 3 - Ns) / 6 / c / 1e9, 4), "unit": "GUpdates/s", "cores": 1, "kind": "oracle",
                "sample": "matrix chain N=%d (same generator), single-thread plain C DP, %.2f s" % (Ns, c)}
+    # the interval-DP cost model's pick for this problem, re-timed beside the fixed tile
+    learned = None
+    try:
+        from paper_1802_00166_amd import tune
+        m = tune.load_default_model("chain")
+        if m is not None:
+            lt, ls, _ = m.predict(tune.problem("matrix_chain", "f64", (N,), pmax), ["slt_wave", "cot_par"])
+            wsl = pc.alloc_workspace(pc.dp_workspace_bytes(N, lt, ls))
+            dtl, _ = _timed(pc, torch, lambda: pc.dp_run(p, pmax, lt, ls, out=C, workspace=wsl),
+                            max(3, args.steps // 2), 1)
+            learned = {"tile_b_b_kchunk": list(lt[1:]), "schedule": ls, "gupd_s": round(upd / dtl / 1e9, 2),
+                       "learned_over_fixed_time": round(dtl / dt, 4)}
+    except ImportError:
+        pass
     # u32 path: v_mul_u32_u24, v_add3_u32, v_min3_u32 per pair of candidate splits -> 2.5 VALU ops/update
-    return _record("GUpdates/s, matrix-chain interval DP N=4096 (exact), tile diagonals", upd / dt / 1e9,
+    rec = _record("GUpdates/s, matrix-chain interval DP N=4096 (exact), tile diagonals", upd / dt / 1e9,
                    "GUpdates/s", args.steps, args.warmup, dt, "u32 (exact; int64 API)",
                    "synthetic: p_i ~ U{1..100} (SplitMix64 stream 5)",
                    {"workload": "matrix_chain_4096_pmax100", "tile_b_b_kchunk": list(tile[1:]), "schedule": sched},
                    _roof(upd, kms / 1e3, 2 * 4 / 32, 2.5), cpu)
+    if learned is not None:
+        rec["model_pick"] = learned
+    return rec
 
 
 def _batch_bytes(tiles, inst):

@@ -16,6 +16,14 @@
 
 Writes DIR/stencil.mlp, DIR/sweeps.json (best of every evaluated sweep) and
 DIR/report.json; the training records go to DIR/records.jsonl.
+
+    python -m paper_1802_00166_amd.train_model --out DIR --chain
+
+trains the interval-DP model instead: sweeps (both schedules, every
+supported (b, k-chunk)) of chains with N uniform in [256, 4096] and pmax in
+{10, 100, 1000} (the 1000 ones take the 64-bit path), then evaluates held-out
+chains, among them N = 4096 with pmax = 100.  Writes DIR/chain.mlp and
+DIR/report_chain.json.
 """
 from __future__ import annotations
 
@@ -69,6 +77,58 @@ def batch_instances(count=256, seed_stream=4):
                 for _ in range(count)]
 
 
+def chain_shapes(n, seed):
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(256, 4097)), int(rng.choice([10, 100, 1000]))) for _ in range(n)]
+
+
+def train_chain(args, tune):
+    """Interval-DP cost model: training sweeps, device training, held-out picks."""
+    two = ["slt_wave", "cot_par"]
+    t_start = time.time()
+    records = []
+    for i, (N, pmax) in enumerate(chain_shapes(args.shapes, args.seed + 11)):
+        t0 = time.time()
+        tile, sched, ms, recs = tune.sweep(tune.problem("matrix_chain", "f64", (N,), pmax), reps=args.reps, warmup=1,
+                                           schedules=two)
+        records += recs
+        log("chain sweep %d/%d N=%d pmax=%d: %d candidates, best %s %s %.3f ms (%.1f s)"
+            % (i + 1, args.shapes, N, pmax, len(recs), tile, sched, ms, time.time() - t0))
+    t0 = time.time()
+    model = tune.Model.train(records, epochs=args.epochs, batch=64, lr=1e-3, seed=args.seed)
+    train_s = time.time() - t0
+    model.save(os.path.join(args.out, "chain.mlp"))
+    pred = model.predict_ms(records)
+    rmse = float(np.sqrt(np.mean((np.log(pred) - np.log([r["ms"] for r in records])) ** 2)))
+    log("trained on %d records in %.2f s, train RMSE(ln ms) %.3f" % (len(records), train_s, rmse))
+    evals, held_sq = [], []
+    for N, pmax in [(4096, 100)] + chain_shapes(6, args.seed + 12):
+        prob = tune.problem("matrix_chain", "f64", (N,), pmax)
+        _, _, _, recs = tune.sweep(prob, reps=args.reps + 2, warmup=1, schedules=two)
+        best = min(recs, key=lambda r: r["ms"])
+        pr = model.predict_ms(recs)
+        held_sq += [float(np.log(pv) - np.log(r["ms"])) ** 2 for pv, r in zip(pr, recs)]
+        _, _, pick_ms, again = tune.tune(prob, tune.TUNE_MODEL_VERIFY, model, reps=args.reps + 2, warmup=1, topk=1,
+                                         schedules=two)
+        e = {"problem": "matrix_chain/N=%d/pmax=%d" % (N, pmax), "sweep_best": [best["tile"], best["schedule"],
+             best["ms"]], "model_pick": [again[0]["tile"], again[0]["schedule"], pick_ms],
+             "pick_over_best": pick_ms / best["ms"]}
+        evals.append(e)
+        log("eval %s: sweep %s %s %.3f ms | model %s %s %.3f ms (x%.3f)" %
+            (e["problem"], best["tile"], best["schedule"], best["ms"], again[0]["tile"], again[0]["schedule"],
+             pick_ms, pick_ms / best["ms"]))
+    ratios = [e["pick_over_best"] for e in evals]
+    rep = {"records": len(records), "train_shapes": args.shapes, "train_seconds": train_s, "train_rmse_ln_ms": rmse,
+           "heldout_rmse_ln_ms": float(np.sqrt(np.mean(held_sq))), "heldout_candidates": len(held_sq),
+           "geomean_pick_over_best": float(math.exp(np.mean(np.log(ratios)))), "max_pick_over_best": max(ratios),
+           "evaluations": evals, "wall_seconds": time.time() - t_start}
+    with open(os.path.join(args.out, "report_chain.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    log("chain model: geomean model/sweep %.4f (max %.4f), held-out RMSE(ln ms) %.3f" %
+        (rep["geomean_pick_over_best"], rep["max_pick_over_best"], rep["heldout_rmse_ln_ms"]))
+    return 0
+
+
 def key_of(kind, dtype, shape, T):
     return "%s/%s/%s/%d" % (kind, dtype, "x".join(str(int(v)) for v in shape), int(T))
 
@@ -90,8 +150,11 @@ def main():
                     help="do not sweep the --shapes set (use with --extra-records holding it)")
     ap.add_argument("--eval-only", metavar="MODEL", default=None,
                     help="skip the training sweeps and training; evaluate this saved model")
+    ap.add_argument("--chain", action="store_true", help="train and evaluate the interval-DP model instead")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
+    if args.chain:
+        return train_chain(args, tune)
     two = ["slt_wave", "cot_par"]
     t_start = time.time()
 

@@ -49,3 +49,18 @@ def test_model_picks_within_ten_percent_of_sweep_and_beat_a_fixed_tile(gpu):
     assert g3 <= 1.10
     assert gm <= 1.20
     assert gg > 1.0
+
+
+def test_chain_model_pick_within_ten_percent_of_sweep(gpu):
+    """The interval-DP model at N = 4096, pmax = 100 (held out of its
+    training sweeps): its pick, re-timed, within 10% of the exhaustive sweep."""
+    from paper_1802_00166_amd import tune
+    model = tune.load_default_model("chain")
+    if model is None:
+        pytest.skip("no stored model (paper_1802_00166_amd/models/chain.mlp)")
+    prob = tune.problem("matrix_chain", "f64", (4096,), 100)
+    two = ["slt_wave", "cot_par"]
+    _, _, best_ms, _ = tune.sweep(prob, reps=5, warmup=1, schedules=two)
+    _, _, pick_ms, _ = tune.tune(prob, tune.TUNE_MODEL_VERIFY, model, reps=5, warmup=1, topk=1, schedules=two)
+    print("chain N=4096: sweep %.3f ms, model %.3f ms (x%.3f)" % (best_ms, pick_ms, pick_ms / best_ms))
+    assert pick_ms <= 1.10 * best_ms
