@@ -124,7 +124,8 @@ pcot_status pcot_stencil_tile_supported(int32_t kind, int32_t dtype, const pcot_
  *          n device pointers.  T, tiles host arrays of n.
  *   workspace >= pcot_stencil_workspace_batched(...).
  * Schedules: PCOT_SLT_WAVE or PCOT_COT_PAR (order within each instance);
- * instances are interleaved heaviest first. */
+ * the instances' tile sequences are interleaved by fractional progress
+ * through each sequence, ties going to the instance with more updates. */
 size_t pcot_stencil_workspace_batched(int32_t kind, int32_t dtype, int32_t n, const int64_t* dims,
                                       const int64_t* T, const pcot_tile* tiles, int32_t schedule);
 pcot_status pcot_stencil_run_batched(int32_t kind, int32_t dtype, int32_t n, const int64_t* dims,
@@ -236,7 +237,7 @@ int64_t pcot_tune_candidates(const pcot_problem* prob, uint32_t sched_mask, pcot
 pcot_status pcot_features(const pcot_problem* prob, const pcot_tile* tile, int32_t schedule, float* feat);
 
 /* Tunes one problem on the GPU: allocates its own buffers (input filled with
- * zeros, DP dims with a valid pattern), times or predicts the candidates per
+ * zeros, DP dims 1 + (37 i mod pmax)), times or predicts the candidates per
  * opts, and returns the best in best/best_sched/best_ms (any may be NULL).
  * Up to `cap` records (every candidate timed or predicted) are written to
  * `records` (may be NULL) and their number to *n_records.  Synchronous. */
