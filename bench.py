@@ -33,7 +33,7 @@ UPDATES = (NY - 2) * (NX - 2) * T
 DEFAULT_TILE = (16, 64, 256)
 DEFAULT_SCHED = "slt_wave"
 # matrix chain N = 4096: (unused, b, b, k-chunk)
-CHAIN_TILE = (0, 32, 32, 64)
+CHAIN_TILE = (0, 32, 32, 32)
 # Heat-3D 512^3, T = 128: the tile each storage type is benchmarked with
 HEAT3D_TILES = {"f64": (2, 64, 16, 64), "f32": (4, 32, 8, 64), "bf16": (4, 32, 8, 64)}
 

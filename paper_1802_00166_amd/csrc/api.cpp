@@ -18,6 +18,7 @@
 #include "plan.hpp"
 
 namespace pcot {
+enum : int { DP_INIT = 0, DP_ITEMS = 1, DP_FINISH = 2 };
 struct DPLaunch {
     const long long* p;
     void* Cw;
@@ -31,7 +32,7 @@ struct DPLaunch {
     long long pmax;
 };
 bool dp_block_supported(int b);
-hipError_t launch_dp_phase(bool wide, const DPLaunch& a, bool init, hipStream_t s);
+hipError_t launch_dp_phase(bool wide, const DPLaunch& a, int mode, hipStream_t s);
 hipError_t launch_dp_pad(const long long* p, long long* pp, int Nout, int N, hipStream_t s);
 }  // namespace pcot
 
@@ -298,16 +299,23 @@ Phases dp_triangle(int i0, int n) {  // tiles (I, J), i0 <= I <= J < i0+n
     return out;
 }
 
+// Per phase q, two launches: the external items of phase-q tiles whose
+// operands include a tile of phase q-1 (`late`), then the finishing pass of
+// phase q together with the external items of phase-(q+1) tiles whose
+// operands were all finished by phase q-1 (`early`), which so run beside a
+// finishing pass instead of after it.
 struct DPPlan {
     int nT = 0, b = 0, kc = 0;
-    std::vector<int> tile_off, item_off;  // per phase, into the arrays below
+    std::vector<int> tile_off, late_off, early_off;  // per phase, into the arrays below
     std::vector<int2> tiles;
-    std::vector<int4> items;
+    std::vector<int4> late, early;
     int2* dtiles = nullptr;
-    int4* ditems = nullptr;
+    int4* dlate = nullptr;
+    int4* dearly = nullptr;
     ~DPPlan() {
         if (dtiles) (void)hipFree(dtiles);
-        if (ditems) (void)hipFree(ditems);
+        if (dlate) (void)hipFree(dlate);
+        if (dearly) (void)hipFree(dearly);
     }
 };
 std::map<std::vector<int64_t>, std::unique_ptr<DPPlan>> g_dp_plans;
@@ -338,25 +346,46 @@ pcot_status get_dp_plan(int nT, int b, int kc, int sched, DPPlan** out) {
     }
     auto P = std::make_unique<DPPlan>();
     P->nT = nT; P->b = b; P->kc = kc;
-    for (auto& q : ph) {
-        P->tile_off.push_back((int)P->tiles.size());
-        P->item_off.push_back((int)P->items.size());
-        for (auto& t : q) {
-            const int ti = (int)P->tiles.size() - P->tile_off.back();
-            P->tiles.push_back(int2{t.first, t.second});
-            if (t.second > t.first) {
-                const int k0 = (t.first + 1) * b - 1, k1 = t.second * b;  // external [k0, k1)
-                for (int k = k0; k < k1; k += kc) P->items.push_back(int4{ti, k, std::min(k + kc, k1), 0});
+    const int nq = (int)ph.size();
+    std::vector<int> phase_of((size_t)nT * nT, 0);
+    for (int q = 0; q < nq; ++q)
+        for (auto& t : ph[q]) phase_of[(size_t)t.first * nT + t.second] = q;
+    std::vector<std::vector<int4>> late(nq), early(nq);
+    for (int q = 0; q < nq; ++q)
+        for (auto& t : ph[q]) {
+            const int I = t.first, J = t.second;
+            if (J == I) continue;
+            const int k0 = (I + 1) * b - 1, k1 = J * b;  // external [k0, k1)
+            for (int k = k0; k < k1; k += kc) {
+                const int ke = std::min(k + kc, k1);
+                // operands C[i][k'] in tiles (I, k'/b) and C[k'+1][j] in tiles ((k'+1)/b, J)
+                int ready = 0;
+                for (int K = k / b; K <= (ke - 1) / b; ++K) ready = std::max(ready, phase_of[(size_t)I * nT + K]);
+                for (int K = (k + 1) / b; K <= ke / b; ++K) ready = std::max(ready, phase_of[(size_t)K * nT + J]);
+                const int4 item = int4{(I << 16) | J, k, ke, 0};
+                if (ready <= q - 2) early[q - 1].push_back(item);
+                else late[q].push_back(item);
             }
         }
+    for (int q = 0; q < nq; ++q) {
+        P->tile_off.push_back((int)P->tiles.size());
+        P->late_off.push_back((int)P->late.size());
+        P->early_off.push_back((int)P->early.size());
+        for (auto& t : ph[q]) P->tiles.push_back(int2{t.first, t.second});
+        P->late.insert(P->late.end(), late[q].begin(), late[q].end());
+        P->early.insert(P->early.end(), early[q].begin(), early[q].end());
     }
     P->tile_off.push_back((int)P->tiles.size());
-    P->item_off.push_back((int)P->items.size());
+    P->late_off.push_back((int)P->late.size());
+    P->early_off.push_back((int)P->early.size());
     HIP_TRY(hipMalloc(&P->dtiles, sizeof(int2) * std::max<size_t>(1, P->tiles.size())));
     HIP_TRY(hipMemcpy(P->dtiles, P->tiles.data(), sizeof(int2) * P->tiles.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&P->ditems, sizeof(int4) * std::max<size_t>(1, P->items.size())));
-    if (!P->items.empty())
-        HIP_TRY(hipMemcpy(P->ditems, P->items.data(), sizeof(int4) * P->items.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&P->dlate, sizeof(int4) * std::max<size_t>(1, P->late.size())));
+    if (!P->late.empty())
+        HIP_TRY(hipMemcpy(P->dlate, P->late.data(), sizeof(int4) * P->late.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&P->dearly, sizeof(int4) * std::max<size_t>(1, P->early.size())));
+    if (!P->early.empty())
+        HIP_TRY(hipMemcpy(P->dearly, P->early.data(), sizeof(int4) * P->early.size(), hipMemcpyHostToDevice));
     *out = P.get();
     g_dp_plans.emplace(key, std::move(P));
     return PCOT_OK;
@@ -789,16 +818,21 @@ pcot_status pcot_dp_run(const int64_t* p, int64_t N, int64_t pmax, const pcot_ti
     L.pmax = pmax;
     HIP_TRY(launch_fill_u32(L.hdr, HDR_WORDS, 0u, s));
     HIP_TRY(launch_dp_pad((const long long*)p, (long long*)(ws + A.pp), (int)N, (int)A.Np, s));
-    HIP_TRY(launch_dp_phase(A.wide, L, true, s));
+    HIP_TRY(launch_dp_phase(A.wide, L, DP_INIT, s));
     hipEvent_t stop;
     st = timed_launch_begin(s, &stop);
     if (st != PCOT_OK) return st;
     for (size_t q = 0; q + 1 < plan->tile_off.size(); ++q) {
+        L.tiles = plan->dtiles;
+        L.ntiles = 0;
+        L.items = plan->dlate + plan->late_off[q];
+        L.nitems = plan->late_off[q + 1] - plan->late_off[q];
+        HIP_TRY(launch_dp_phase(A.wide, L, DP_ITEMS, s));
         L.tiles = plan->dtiles + plan->tile_off[q];
         L.ntiles = plan->tile_off[q + 1] - plan->tile_off[q];
-        L.items = plan->ditems + plan->item_off[q];
-        L.nitems = plan->item_off[q + 1] - plan->item_off[q];
-        HIP_TRY(launch_dp_phase(A.wide, L, false, s));
+        L.items = plan->dearly + plan->early_off[q];
+        L.nitems = plan->early_off[q + 1] - plan->early_off[q];
+        HIP_TRY(launch_dp_phase(A.wide, L, DP_FINISH, s));
     }
     return timed_launch_end(s, stop);
 }

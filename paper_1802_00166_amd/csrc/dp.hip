@@ -24,6 +24,8 @@
 
 namespace pcot {
 
+enum : int { DP_INIT = 0, DP_ITEMS = 1, DP_FINISH = 2 };
+
 struct DPLaunch {
     const long long* p;  // N+1 dimensions (device)
     void* Cw;            // working matrix, N x N, u32 or i64 (device)
@@ -31,7 +33,7 @@ struct DPLaunch {
     int N, Nout, b;      // N: padded to a multiple of b (dims past Nout are 1)
     const int2* tiles;   // (I, J) of the phase (device)
     int ntiles;
-    const int4* items;   // external work items: (tile index, k_begin, k_end, 0)
+    const int4* items;   // external work items: ((I << 16) | J, k_begin, k_end, 0)
     int nitems;
     unsigned* hdr;
     long long pmax;
@@ -93,16 +95,15 @@ __global__ void k_dp_init(DPLaunch a) {
 // owns an R x R micro-tile; operand tiles go through LDS in KT-deep slices
 // (A transposed so a thread's R rows are contiguous).
 template <typename V, int B, int R>
-__global__ void __launch_bounds__(256) k_dp_ext(DPLaunch a) {
+__device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
     constexpr int KT = 16;
     constexpr int TPR = B / R;  // threads per row of micro-tiles (TPR*TPR == 256)
     static_assert(TPR * TPR == 256, "micro-tile layout");
     __shared__ V As[KT][B];     // As[kk][r] = C[I*B + r][k0 + kk]
     __shared__ V Bs[KT][B];     // Bs[kk][c] = C[k0 + kk + 1][J*B + c]
     __shared__ V Ps[KT];        // p[k + 1]
-    const int4 it = a.items[blockIdx.x];
-    const int2 tj = a.tiles[it.x];
-    const int I = tj.x, J = tj.y;
+    const int4 it = a.items[item];
+    const int I = it.x >> 16, J = it.x & 0xFFFF;  // target tile (I, J)
     const int N = a.N;
     const V* Cw = (const V*)a.Cw;
     const int tid = threadIdx.x;
@@ -186,14 +187,14 @@ __device__ __forceinline__ V group_min(V v) {
 // or left of it (same row), i.e. on earlier anti-diagonals.  Each cell is
 // handled by TPC threads that split its internal k range, then min-reduce.
 template <typename V, int B>
-__global__ void __launch_bounds__(256) k_dp_fin(DPLaunch a) {
+__device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
     constexpr int TPC = 256 / B;  // threads per cell
     __shared__ V T[B][B + 1];     // tile (I, J)
     __shared__ V DI[B][B + 1];    // tile (I, I) (unused when I == J)
     __shared__ V DJ[B][B + 1];    // tile (J, J) (unused when I == J)
     __shared__ V PA[B + 1];  // p[I*B .. I*B + B]: p[i] of the tile's rows, p[k+1] for k in block I
     __shared__ V PB[B];      // p[J*B + 1 .. J*B + B]: p[j+1] of its columns, p[k+1] for k in block J
-    const int2 tj = a.tiles[blockIdx.x];
+    const int2 tj = a.tiles[tile];
     const int I = tj.x, J = tj.y;
     const int N = a.N;
     V* Cw = (V*)a.Cw;
@@ -269,15 +270,37 @@ __global__ void __launch_bounds__(256) k_dp_fin(DPLaunch a) {
     }
 }
 
+// External items alone (they need the tiles finished by the previous launch).
+template <typename V, int B, int R>
+__global__ void __launch_bounds__(256) k_dp_ext(DPLaunch a) {
+    dp_ext_item<V, B, R>(a, blockIdx.x);
+}
+
+// A phase's finishing pass together with the external items of the next
+// phase whose operand tiles were finished before this launch: blocks
+// [0, ntiles) finish tiles, the rest take items.  The two sets touch
+// disjoint tiles (items only read finished tiles and atomically lower cells
+// of next-phase tiles).
+template <typename V, int B, int R>
+__global__ void __launch_bounds__(256) k_dp_fin(DPLaunch a) {
+    if ((int)blockIdx.x < a.ntiles)
+        dp_fin_tile<V, B>(a, blockIdx.x);
+    else
+        dp_ext_item<V, B, R>(a, blockIdx.x - a.ntiles);
+}
+
 template <typename V, int B>
-hipError_t launch_phase_t(const DPLaunch& a, bool init, hipStream_t s) {
-    if (init) {
+hipError_t launch_phase_t(const DPLaunch& a, int mode, hipStream_t s) {
+    if (mode == DP_INIT) {
         hipLaunchKernelGGL((k_dp_init<V>), dim3(2048), dim3(256), 0, s, a);
         return hipGetLastError();
     }
     constexpr int R = B == 32 ? 2 : (B == 64 ? 4 : 8);
-    if (a.nitems > 0) hipLaunchKernelGGL((k_dp_ext<V, B, R>), dim3(a.nitems), dim3(256), 0, s, a);
-    if (a.ntiles > 0) hipLaunchKernelGGL((k_dp_fin<V, B>), dim3(a.ntiles), dim3(256), 0, s, a);
+    if (mode == DP_ITEMS) {
+        if (a.nitems > 0) hipLaunchKernelGGL((k_dp_ext<V, B, R>), dim3(a.nitems), dim3(256), 0, s, a);
+    } else if (a.ntiles + a.nitems > 0) {
+        hipLaunchKernelGGL((k_dp_fin<V, B, R>), dim3(a.ntiles + a.nitems), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -290,15 +313,15 @@ hipError_t launch_dp_pad(const long long* p, long long* pp, int Nout, int N, hip
     return hipGetLastError();
 }
 
-// One phase: external items then the finishing pass of the phase's tiles
-// (or, with init, the initialisation of the working matrices).
-hipError_t launch_dp_phase(bool wide, const DPLaunch& a, bool init, hipStream_t s) {
+// One launch of a DP plan: the initialisation of the working matrices, a set
+// of external items, or a finishing pass with the items that run beside it.
+hipError_t launch_dp_phase(bool wide, const DPLaunch& a, int mode, hipStream_t s) {
     if (!wide) {
-        if (a.b == 32) return launch_phase_t<unsigned, 32>(a, init, s);
-        return launch_phase_t<unsigned, 64>(a, init, s);
+        if (a.b == 32) return launch_phase_t<unsigned, 32>(a, mode, s);
+        return launch_phase_t<unsigned, 64>(a, mode, s);
     }
-    if (a.b == 32) return launch_phase_t<long long, 32>(a, init, s);
-    return launch_phase_t<long long, 64>(a, init, s);
+    if (a.b == 32) return launch_phase_t<long long, 32>(a, mode, s);
+    return launch_phase_t<long long, 64>(a, mode, s);
 }
 
 }  // namespace pcot
