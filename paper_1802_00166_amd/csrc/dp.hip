@@ -94,7 +94,9 @@ __global__ void k_dp_init(DPLaunch a) {
 // One block per work item: a B x B output tile, k in [k0, k1).  Each thread
 // owns an R x R micro-tile; operand tiles go through LDS in KT-deep slices
 // (A transposed so a thread's R rows are contiguous).
-template <typename V, int B, int R>
+// NT threads per block; the first 256 own the micro-tiles, the rest (when
+// NT = 512, in the launch shared with a finishing pass) only help stage.
+template <typename V, int B, int R, int NT>
 __device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
     constexpr int KT = 16;
     constexpr int TPR = B / R;  // threads per row of micro-tiles (TPR*TPR == 256)
@@ -107,7 +109,8 @@ __device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
     const int N = a.N;
     const V* Cw = (const V*)a.Cw;
     const int tid = threadIdx.x;
-    const int tr = tid / TPR, tc = tid % TPR;  // micro-tile coordinates
+    const bool on = tid < 256;
+    const int tr = (tid & 255) / TPR, tc = tid % TPR;  // micro-tile coordinates
     const int row0 = I * B + tr * R, col0 = J * B + tc * R;
     V w[R][R], m[R][R];
 #pragma unroll
@@ -119,7 +122,7 @@ __device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
         }
     for (int k0 = it.y; k0 < it.z; k0 += KT) {
         // stage KT columns of the row panel and KT rows of the column panel
-        for (int e = tid; e < KT * B; e += 256) {
+        for (int e = tid; e < KT * B; e += NT) {
             const int kk = e / B, x = e % B;
             const int k = k0 + kk;
             const bool ok = k < it.z;
@@ -130,7 +133,7 @@ __device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
         if (tid < KT) Ps[tid] = (k0 + tid < it.z) ? (V)a.p[k0 + tid + 1] : (V)0;
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < KT; ++kk) {
+        for (int kk = 0; kk < (on ? KT : 0); ++kk) {
             V av[R], bv[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) av[r] = As[kk][tr * R + r];
@@ -148,21 +151,24 @@ __device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
         __syncthreads();
     }
     V* Cm = (V*)a.Cw;
+    if (on) {
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int c = 0; c < R; ++c) DV<V>::amin(Cm + (size_t)(row0 + r) * N + col0 + c, m[r][c]);
+            for (int c = 0; c < R; ++c) DV<V>::amin(Cm + (size_t)(row0 + r) * N + col0 + c, m[r][c]);
+    }
 }
 
-// Minimum over groups of TPC adjacent lanes (TPC in {2, 4, 8}) with DPP lane
-// moves: swap neighbours, swap pairs within a quad, then mirror the two quads
-// of each half row (lane i of the 8 meets lane 7-i), so every lane ends with
-// the group's minimum.
+// Minimum over groups of TPC adjacent lanes (TPC in {2, 4, 8, 16}) with DPP
+// lane moves: swap neighbours, swap pairs within a quad, mirror the two quads
+// of each half row (lane i of the 8 meets lane 7-i), then mirror the row of
+// 16, so every lane ends with the group's minimum.
 __device__ __forceinline__ unsigned dpp_move(unsigned v, int ctrl) {
     switch (ctrl) {
         case 0: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
         case 1: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
-        default: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false); // row_half_mirror
+        case 2: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+        default: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false); // row_mirror
     }
 }
 __device__ __forceinline__ long long dpp_move(long long v, int ctrl) {
@@ -172,7 +178,7 @@ __device__ __forceinline__ long long dpp_move(long long v, int ctrl) {
 }
 template <int TPC, typename V>
 __device__ __forceinline__ V group_min(V v) {
-    static_assert(TPC == 2 || TPC == 4 || TPC == 8, "group of 2, 4 or 8 lanes");
+    static_assert(TPC == 2 || TPC == 4 || TPC == 8 || TPC == 16, "group of 2, 4, 8 or 16 lanes");
 #pragma unroll
     for (int c = 0; (1 << c) < TPC; ++c) {
         const V o = dpp_move(v, c);
@@ -186,9 +192,9 @@ __device__ __forceinline__ V group_min(V v) {
 // ((I+1)B-1-i, j-JB): a cell's internal operands lie below it (same column)
 // or left of it (same row), i.e. on earlier anti-diagonals.  Each cell is
 // handled by TPC threads that split its internal k range, then min-reduce.
-template <typename V, int B>
+template <typename V, int B, int NT>
 __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
-    constexpr int TPC = 256 / B;  // threads per cell
+    constexpr int TPC = NT / B;  // threads per cell
     __shared__ V T[B][B + 1];     // tile (I, J)
     __shared__ V DI[B][B + 1];    // tile (I, I) (unused when I == J)
     __shared__ V DJ[B][B + 1];    // tile (J, J) (unused when I == J)
@@ -200,7 +206,7 @@ __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
     V* Cw = (V*)a.Cw;
     const int tid = threadIdx.x;
     const bool diag = I == J;
-    for (int e = tid; e < B * B; e += 256) {
+    for (int e = tid; e < B * B; e += NT) {
         const int r = e / B, c = e % B;
         T[r][c] = Cw[(size_t)(I * B + r) * N + J * B + c];
         if (!diag) {
@@ -259,7 +265,7 @@ __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
         }
         __syncthreads();
     }
-    for (int e = tid; e < B * B; e += 256) {
+    for (int e = tid; e < B * B; e += NT) {
         const int r = e / B, c = e % B;
         const int gi = I * B + r, gj = J * B + c;
         if (gi <= gj) {
@@ -273,7 +279,7 @@ __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
 // External items alone (they need the tiles finished by the previous launch).
 template <typename V, int B, int R>
 __global__ void __launch_bounds__(256) k_dp_ext(DPLaunch a) {
-    dp_ext_item<V, B, R>(a, blockIdx.x);
+    dp_ext_item<V, B, R, 256>(a, blockIdx.x);
 }
 
 // A phase's finishing pass together with the external items of the next
@@ -281,12 +287,13 @@ __global__ void __launch_bounds__(256) k_dp_ext(DPLaunch a) {
 // [0, ntiles) finish tiles, the rest take items.  The two sets touch
 // disjoint tiles (items only read finished tiles and atomically lower cells
 // of next-phase tiles).
+// 512 threads: a cell of the finishing pass gets 512 / B lanes.
 template <typename V, int B, int R>
-__global__ void __launch_bounds__(256) k_dp_fin(DPLaunch a) {
+__global__ void __launch_bounds__(512) k_dp_fin(DPLaunch a) {
     if ((int)blockIdx.x < a.ntiles)
-        dp_fin_tile<V, B>(a, blockIdx.x);
+        dp_fin_tile<V, B, 512>(a, blockIdx.x);
     else
-        dp_ext_item<V, B, R>(a, blockIdx.x - a.ntiles);
+        dp_ext_item<V, B, R, 512>(a, blockIdx.x - a.ntiles);
 }
 
 template <typename V, int B>
@@ -299,7 +306,7 @@ hipError_t launch_phase_t(const DPLaunch& a, int mode, hipStream_t s) {
     if (mode == DP_ITEMS) {
         if (a.nitems > 0) hipLaunchKernelGGL((k_dp_ext<V, B, R>), dim3(a.nitems), dim3(256), 0, s, a);
     } else if (a.ntiles + a.nitems > 0) {
-        hipLaunchKernelGGL((k_dp_fin<V, B, R>), dim3(a.ntiles + a.nitems), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_dp_fin<V, B, R>), dim3(a.ntiles + a.nitems), dim3(512), 0, s, a);
     }
     return hipGetLastError();
 }
