@@ -95,7 +95,7 @@ __global__ void k_dp_init(DPLaunch a) {
 // owns an R x R micro-tile; operand tiles go through LDS in KT-deep slices
 // (A transposed so a thread's R rows are contiguous).
 // NT threads per block; the first 256 own the micro-tiles, the rest (when
-// NT = 512, in the launch shared with a finishing pass) only help stage.
+// NT > 256, in the launch shared with a finishing pass) only help stage.
 template <typename V, int B, int R, int NT>
 __device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
     constexpr int KT = 16;
@@ -159,16 +159,18 @@ __device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
     }
 }
 
-// Minimum over groups of TPC adjacent lanes (TPC in {2, 4, 8, 16}) with DPP
+// Minimum over groups of TPC adjacent lanes (TPC in {2, ..., 32}) with DPP
 // lane moves: swap neighbours, swap pairs within a quad, mirror the two quads
-// of each half row (lane i of the 8 meets lane 7-i), then mirror the row of
-// 16, so every lane ends with the group's minimum.
+// of each half row (lane i of the 8 meets lane 7-i), mirror the row of 16,
+// then exchange the two rows of 32 (swizzle, lane ^ 16), so every lane ends
+// with the group's minimum.
 __device__ __forceinline__ unsigned dpp_move(unsigned v, int ctrl) {
     switch (ctrl) {
         case 0: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
         case 1: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
         case 2: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-        default: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false); // row_mirror
+        case 3: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+        default: return (unsigned)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);  // lane ^ 16 within 32 lanes
     }
 }
 __device__ __forceinline__ long long dpp_move(long long v, int ctrl) {
@@ -178,7 +180,7 @@ __device__ __forceinline__ long long dpp_move(long long v, int ctrl) {
 }
 template <int TPC, typename V>
 __device__ __forceinline__ V group_min(V v) {
-    static_assert(TPC == 2 || TPC == 4 || TPC == 8 || TPC == 16, "group of 2, 4, 8 or 16 lanes");
+    static_assert(TPC == 2 || TPC == 4 || TPC == 8 || TPC == 16 || TPC == 32, "group of 2 to 32 lanes");
 #pragma unroll
     for (int c = 0; (1 << c) < TPC; ++c) {
         const V o = dpp_move(v, c);
@@ -287,13 +289,13 @@ __global__ void __launch_bounds__(256) k_dp_ext(DPLaunch a) {
 // [0, ntiles) finish tiles, the rest take items.  The two sets touch
 // disjoint tiles (items only read finished tiles and atomically lower cells
 // of next-phase tiles).
-// 512 threads: a cell of the finishing pass gets 512 / B lanes.
+// 1024 threads: a cell of the finishing pass gets 1024 / B lanes.
 template <typename V, int B, int R>
-__global__ void __launch_bounds__(512) k_dp_fin(DPLaunch a) {
+__global__ void __launch_bounds__(1024) k_dp_fin(DPLaunch a) {
     if ((int)blockIdx.x < a.ntiles)
-        dp_fin_tile<V, B, 512>(a, blockIdx.x);
+        dp_fin_tile<V, B, 1024>(a, blockIdx.x);
     else
-        dp_ext_item<V, B, R, 512>(a, blockIdx.x - a.ntiles);
+        dp_ext_item<V, B, R, 1024>(a, blockIdx.x - a.ntiles);
 }
 
 template <typename V, int B>
@@ -306,7 +308,7 @@ hipError_t launch_phase_t(const DPLaunch& a, int mode, hipStream_t s) {
     if (mode == DP_ITEMS) {
         if (a.nitems > 0) hipLaunchKernelGGL((k_dp_ext<V, B, R>), dim3(a.nitems), dim3(256), 0, s, a);
     } else if (a.ntiles + a.nitems > 0) {
-        hipLaunchKernelGGL((k_dp_fin<V, B, R>), dim3(a.ntiles + a.nitems), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_dp_fin<V, B, R>), dim3(a.ntiles + a.nitems), dim3(1024), 0, s, a);
     }
     return hipGetLastError();
 }
