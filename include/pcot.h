@@ -75,6 +75,7 @@ typedef int32_t pcot_status;
 #define PCOT_ERR_WORKSPACE (-5)   /* workspace missing or smaller than required            */
 #define PCOT_ERR_TIMEOUT (-6)     /* device watchdog: a tile waited too long for its inputs */
 #define PCOT_ERR_DEVICE (-7)      /* device-side validation failed (e.g. p out of range)    */
+#define PCOT_ERR_HOST (-8)        /* host-side failure (out of host memory for a plan)      */
 
 /* Leaf (tile) sizes.  t: time steps per tile; s[0..d-1]: spatial sizes, outer
  * to inner, in skewed coordinates (j = i + t).  The same numbers are the
@@ -108,7 +109,13 @@ size_t pcot_stencil_workspace(int32_t kind, int32_t dtype, const int64_t* dims, 
  *             a workspace must be ordered on one stream.
  * Every schedule and every valid tile gives the same bits (the method only
  * reorders points of a fully permutable nest; each point uses the fixed
- * operation order of its update rule, without contraction to FMA). */
+ * operation order of its update rule, without contraction to FMA).
+ * Size limit of the tiled schedules: the executors address a field with
+ * 32-bit byte offsets, so field bytes + 2 outermost slices (rows in 2D,
+ * planes in 3D) + 4 KiB must stay below 0x7FFFFFF0 (just under 2 GiB);
+ * larger fields return PCOT_ERR_UNSUPPORTED here and from
+ * pcot_stencil_workspace (0) and the batched calls.  PCOT_NAIVE has no such
+ * limit. */
 pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T,
                              const pcot_tile* tile, int32_t schedule, const void* in, void* out,
                              void* workspace, size_t ws_bytes, void* stream);
@@ -167,7 +174,10 @@ pcot_status pcot_error_norms(int32_t dtype, int32_t d, const int64_t* dims, cons
  *   schedule PCOT_SLT_WAVE (tile diagonals in order) or PCOT_COT_PAR
  *          (recursive halving of the padded (i, j) triangle; leaves grouped by
  *          the wavefronts of each split).
- * Every schedule and tile gives identical (exact integer) results. */
+ * Every schedule and tile gives identical (exact integer) results.
+ * Plan limit: the off-diagonal k range of every tile pair is cut into
+ * k-chunk items; more than 2^31-1 items (e.g. N = 65536 with b = 32 and
+ * k-chunk 16) returns PCOT_ERR_UNSUPPORTED. */
 size_t pcot_dp_workspace(int64_t N, const pcot_tile* tile, int32_t schedule);
 pcot_status pcot_dp_run(const int64_t* p, int64_t N, int64_t pmax, const pcot_tile* tile,
                         int32_t schedule, int64_t* C, void* workspace, size_t ws_bytes,

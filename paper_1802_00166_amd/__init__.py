@@ -31,7 +31,7 @@ KINDS = {"jacobi1d": JACOBI1D, "jacobi2d": JACOBI2D, "heat3d": HEAT3D}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 SCHEDULES = {"naive": NAIVE, "slt_lex": SLT_LEX, "slt_wave": SLT_WAVE, "cot_seq": COT_SEQ, "cot_par": COT_PAR}
 STATUS = {0: "OK", -1: "INVALID", -2: "UNSUPPORTED", -3: "OVERFLOW", -4: "HIP", -5: "WORKSPACE",
-          -6: "TIMEOUT", -7: "DEVICE"}
+          -6: "TIMEOUT", -7: "DEVICE", -8: "HOST"}
 
 
 class pcot_tile(ctypes.Structure):

@@ -62,6 +62,9 @@ namespace {
     } while (0)
 
 constexpr size_t ALIGN = 256;
+// First byte offset the tiled executors treat as out of range (the store
+// mask offset of their buffer resources).
+constexpr uint32_t TILED_MAX_OFFSET = 0x7FFFFFF0u;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 size_t elem_bytes(int dtype) { return dtype == PCOT_F64 ? 8 : dtype == PCOT_F32 ? 4 : 2; }
@@ -117,7 +120,17 @@ pcot_status validate(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T
             if (tile->s[i] < 2) return fail(PCOT_ERR_INVALID, "tile.s[%d]=%d < 2 (dependence distance is 2)", i, tile->s[i]);
             p.b[i + 1] = tile->s[i];
         }
-        if (p.elems > (1LL << 31) - 1) return fail(PCOT_ERR_UNSUPPORTED, "tiled executors index fields below 2^31 elements");
+        // The tiled executors address a field through one buffer resource
+        // with 32-bit byte offsets and mask stores with the offset OOB
+        // (0x7FFFFFF0).  Offsets they form reach one outermost slice (row,
+        // plane) past either end of the array, so the field plus two such
+        // slices must stay below OOB.
+        const int64_t es = (int64_t)elem_bytes(dtype);
+        const int64_t slice = p.elems / p.n[0] * es;
+        if (p.elems * es + 2 * slice + 4096 > (int64_t)TILED_MAX_OFFSET)
+            return fail(PCOT_ERR_UNSUPPORTED,
+                        "field of %lld bytes: the tiled executors need field + 2 outer slices + 4 KiB below %lld bytes",
+                        (long long)(p.elems * es), (long long)TILED_MAX_OFFSET);
     }
     return PCOT_OK;
 }
@@ -411,6 +424,17 @@ pcot_status dp_validate(int64_t N, int64_t pmax, const pcot_tile* tile, int32_t 
     if (!dp_block_supported(A.b)) return fail(PCOT_ERR_UNSUPPORTED, "DP block size %d (supported: 32, 64)", A.b);
     if (A.kc < 16 || A.kc % 16) return fail(PCOT_ERR_INVALID, "DP k-chunk %d: multiple of 16 required", A.kc);
     A.Np = (N + A.b - 1) / A.b * A.b;
+    {
+        // external items (one per tile pair and k-chunk of the off-diagonal
+        // k range) are indexed with int offsets in the plan: bound their count
+        const int64_t nT = A.Np / A.b;
+        int64_t items = 0;
+        for (int64_t d = 1; d < nT; ++d)
+            items += (nT - d) * (((d - 1) * A.b + 1 + A.kc - 1) / A.kc);
+        if (items > (int64_t)INT32_MAX)
+            return fail(PCOT_ERR_UNSUPPORTED, "DP plan of %lld k-chunk items exceeds 2^31-1 (use a larger k-chunk or block)",
+                        (long long)items);
+    }
     // exactness: every candidate is at most (N-1) * pmax^3
     const long double bound = (long double)(N > 1 ? N - 1 : 1) * (long double)pmax * pmax * pmax;
     if (pmax < 1) return fail(PCOT_ERR_INVALID, "pmax=%lld < 1", (long long)pmax);
@@ -585,12 +609,15 @@ const char* pcot_version(void) { return "pcot-mi355x 0.1 (gfx950)"; }
 
 size_t pcot_stencil_workspace(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T, const pcot_tile* tile,
                               int32_t schedule) {
+    PCOT_TRY
     Prob p;
     if (validate(kind, dtype, dims, T, tile, schedule, p) != PCOT_OK) return 0;
     return ws_layout(p).total;
+    PCOT_CATCH(0)
 }
 
 pcot_status pcot_stencil_tile_supported(int32_t kind, int32_t dtype, const pcot_tile* tile) {
+    PCOT_TRY
     const int d = kind_dims(kind);
     if (!d) return fail(PCOT_ERR_INVALID, "unknown kind %d", kind);
     if (dtype < PCOT_F64 || dtype > PCOT_BF16) return fail(PCOT_ERR_INVALID, "unknown dtype %d", dtype);
@@ -602,10 +629,12 @@ pcot_status pcot_stencil_tile_supported(int32_t kind, int32_t dtype, const pcot_
     }
     if (!tile_ok(kind, dtype, b)) return fail(PCOT_ERR_UNSUPPORTED, "tile (%d; %d,%d,%d) not runnable for kind %d dtype %d", b[0], b[1], b[2], b[3], kind, dtype);
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 int64_t pcot_stencil_plan(int32_t kind, const int64_t* dims, int64_t T, const pcot_tile* tile, int32_t schedule,
                           int32_t* order, int64_t cap) {
+    PCOT_TRY
     Prob p;
     if (schedule == PCOT_NAIVE) { fail(PCOT_ERR_INVALID, "naive schedule has no plan"); return -1; }
     if (validate(kind, PCOT_F64, dims, T, tile, schedule, p) != PCOT_OK) return -1;
@@ -615,11 +644,13 @@ int64_t pcot_stencil_plan(int32_t kind, const int64_t* dims, int64_t T, const pc
         for (int64_t i = 0; i < (int64_t)leaves.size() && i < cap; ++i)
             for (int j = 0; j < 4; ++j) order[4 * i + j] = leaves[i].k[j];
     return (int64_t)leaves.size();
+    PCOT_CATCH(-1)
 }
 
 pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T, const pcot_tile* tile,
                              int32_t schedule, const void* in, void* out, void* workspace, size_t ws_bytes,
                              void* stream) {
+    PCOT_TRY
     Prob p;
     pcot_status st = validate(kind, dtype, dims, T, tile, schedule, p);
     if (st != PCOT_OK) return st;
@@ -687,19 +718,23 @@ pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, i
     if (st != PCOT_OK) return st;
     HIP_TRY(launch_tiled_kind(kind, dtype, p.b, L, 0, s));
     return timed_launch_end(s, stop);
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 size_t pcot_stencil_workspace_batched(int32_t kind, int32_t dtype, int32_t n, const int64_t* dims,
                                       const int64_t* T, const pcot_tile* tiles, int32_t schedule) {
+    PCOT_TRY
     Batch B;
     if (batch_validate(kind, dtype, n, dims, T, tiles, schedule, B) != PCOT_OK) return 0;
     return batch_layout(B).total;
+    PCOT_CATCH(0)
 }
 
 pcot_status pcot_stencil_run_batched(int32_t kind, int32_t dtype, int32_t n, const int64_t* dims,
                                      const int64_t* T, const pcot_tile* tiles, int32_t schedule,
                                      const void* const* in, void* const* out, void* workspace, size_t ws_bytes,
                                      void* stream) {
+    PCOT_TRY
     Batch B;
     pcot_status st = batch_validate(kind, dtype, n, dims, T, tiles, schedule, B);
     if (st != PCOT_OK) return st;
@@ -761,10 +796,12 @@ pcot_status pcot_stencil_run_batched(int32_t kind, int32_t dtype, int32_t n, con
     if (st != PCOT_OK) return st;
     HIP_TRY(launch_tiled_kind(kind, dtype, B.lb, L, 0, s));
     return timed_launch_end(s, stop);
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_error_norms(int32_t dtype, int32_t d, const int64_t* dims, const void* x, const double* r,
                              double* out, void* stream) {
+    PCOT_TRY
     if (dtype < PCOT_F64 || dtype > PCOT_BF16) return fail(PCOT_ERR_INVALID, "unknown dtype %d", dtype);
     if (d < 1 || d > 3) return fail(PCOT_ERR_INVALID, "d=%d (need 1..3)", d);
     if (!dims || !x || !r || !out) return fail(PCOT_ERR_INVALID, "NULL argument");
@@ -784,17 +821,21 @@ pcot_status pcot_error_norms(int32_t dtype, int32_t d, const int64_t* dims, cons
     HIP_TRY(hipMemcpyAsync(out, scratch + res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 size_t pcot_dp_workspace(int64_t N, const pcot_tile* tile, int32_t schedule) {
+    PCOT_TRY
     DPArgs A;
     // the 64-bit working matrix is the larger case; size for it
     if (dp_validate(N, 1, tile, schedule, A) != PCOT_OK) return 0;
     return A.cw + align_up(8 * (size_t)A.Np * A.Np);
+    PCOT_CATCH(0)
 }
 
 pcot_status pcot_dp_run(const int64_t* p, int64_t N, int64_t pmax, const pcot_tile* tile, int32_t schedule,
                         int64_t* C, void* workspace, size_t ws_bytes, void* stream) {
+    PCOT_TRY
     DPArgs A;
     pcot_status st = dp_validate(N, pmax, tile, schedule, A);
     if (st != PCOT_OK) return st;
@@ -835,9 +876,11 @@ pcot_status pcot_dp_run(const int64_t* p, int64_t N, int64_t pmax, const pcot_ti
         HIP_TRY(launch_dp_phase(A.wide, L, DP_FINISH, s));
     }
     return timed_launch_end(s, stop);
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_stream_status(void* workspace, void* stream) {
+    PCOT_TRY
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     if (!workspace) return fail(PCOT_ERR_INVALID, "workspace is NULL");
     unsigned w = 0;
@@ -846,9 +889,11 @@ pcot_status pcot_stream_status(void* workspace, void* stream) {
     if (w == DEVERR_INPUT) return fail(PCOT_ERR_DEVICE, "device validation failed (input out of the stated range)");
     if (w != 0) return fail(PCOT_ERR_DEVICE, "device error word %u", w);
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_kernel_timing(int32_t enable) {
+    PCOT_TRY
     std::lock_guard<std::mutex> lk(g_tmu);
     for (auto& e : g_events) {
         (void)hipEventDestroy(e.first);
@@ -857,9 +902,11 @@ pcot_status pcot_kernel_timing(int32_t enable) {
     g_events.clear();
     g_timing = enable != 0;
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_kernel_timing_read(double* total_ms, int64_t* count) {
+    PCOT_TRY
     std::lock_guard<std::mutex> lk(g_tmu);
     double tot = 0.0;
     for (auto& e : g_events) {
@@ -871,6 +918,7 @@ pcot_status pcot_kernel_timing_read(double* total_ms, int64_t* count) {
     if (total_ms) *total_ms = tot;
     if (count) *count = (int64_t)g_events.size();
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 

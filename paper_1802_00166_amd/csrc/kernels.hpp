@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <exception>
+#include <new>
 
 namespace pcot {
 
@@ -64,6 +66,26 @@ hipError_t launch_norms(int dtype, int d, const int64_t* n, const void* x, const
 
 // Sets the thread's last-error message and returns `code` (api.cpp).
 int32_t fail(int32_t code, const char* fmt, ...);
+
+// No C++ exception may cross the C ABI: every extern "C" entry point wraps
+// its body in PCOT_TRY ... PCOT_CATCH(value returned on failure), which turns
+// a host allocation failure (std::bad_alloc from a plan or sweep container)
+// or any other exception into PCOT_ERR_HOST with a message.
+#define PCOT_TRY try {
+#define PCOT_CATCH(onerr)                                                                 \
+    }                                                                                     \
+    catch (const std::bad_alloc&) {                                                       \
+        pcot::fail(-8, "host memory allocation failed");                                  \
+        return onerr;                                                                     \
+    }                                                                                     \
+    catch (const std::exception& e_) {                                                    \
+        pcot::fail(-8, "host exception: %s", e_.what());                                  \
+        return onerr;                                                                     \
+    }                                                                                     \
+    catch (...) {                                                                         \
+        pcot::fail(-8, "unknown host exception");                                         \
+        return onerr;                                                                     \
+    }
 
 // Cost-model MLP (8 -> 64 -> 64 -> 1, binary32), see mlp.hip.
 constexpr int MLP_NP = 4801;

@@ -208,6 +208,7 @@ extern "C" {
 
 int64_t pcot_tune_candidates(const pcot_problem* prob, uint32_t sched_mask, pcot_tile* tiles, int32_t* scheds,
                              int64_t cap) {
+    PCOT_TRY
     if (!valid_problem(prob)) {
         fail(PCOT_ERR_INVALID, "invalid problem");
         return -1;
@@ -218,16 +219,20 @@ int64_t pcot_tune_candidates(const pcot_problem* prob, uint32_t sched_mask, pcot
         if (scheds) scheds[i] = c[i].second;
     }
     return (int64_t)c.size();
+    PCOT_CATCH(-1)
 }
 
 pcot_status pcot_features(const pcot_problem* prob, const pcot_tile* tile, int32_t schedule, float* feat) {
+    PCOT_TRY
     if (!valid_problem(prob) || !tile || !feat) return fail(PCOT_ERR_INVALID, "invalid problem, tile or feat");
     features(prob, tile, schedule, feat);
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_tune(const pcot_problem* prob, const pcot_tune_opts* opts, pcot_tile* best, int32_t* best_sched,
                       double* best_ms, pcot_record* records, size_t cap, size_t* n_records, void* stream) {
+    PCOT_TRY
     if (!valid_problem(prob)) return fail(PCOT_ERR_INVALID, "invalid problem");
     pcot_tune_opts o;
     memset(&o, 0, sizeof o);
@@ -317,10 +322,12 @@ pcot_status pcot_tune(const pcot_problem* prob, const pcot_tune_opts* opts, pcot
     }
     if (n_records) *n_records = records ? k : (timed.empty() ? nc : timed.size());
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 // ------------------------------------------------------------------ MLP ---
 pcot_status pcot_mlp_forward(const float* params, const float* X, int32_t n, float* yhat, void* stream) {
+    PCOT_TRY
     if (!params || !X || !yhat || n < 0) return fail(PCOT_ERR_INVALID, "NULL argument or n < 0");
     if (n == 0) return PCOT_OK;
     hipStream_t st = (hipStream_t)stream;
@@ -334,10 +341,12 @@ pcot_status pcot_mlp_forward(const float* params, const float* X, int32_t n, flo
     HIP_TRY(hipMemcpyAsync(yhat, dy.p, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_mlp_grad(const float* params, const float* X, const float* y, int32_t n, float* grad, float* loss,
                           void* stream) {
+    PCOT_TRY
     if (!params || !X || !y || !grad || n < 1 || n > 256) return fail(PCOT_ERR_INVALID, "bad argument (1 <= n <= 256)");
     hipStream_t st = (hipStream_t)stream;
     std::vector<int> rows(n);
@@ -362,11 +371,13 @@ pcot_status pcot_mlp_grad(const float* params, const float* X, const float* y, i
     HIP_TRY(hipStreamSynchronize(st));
     if (loss) *loss = l;
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_mlp_train(float* params, float* m, float* v, const float* X, const float* y, int32_t n,
                            const int32_t* order, int32_t epochs, int32_t batch, int32_t step0, float lr,
                            float* epoch_loss, void* stream) {
+    PCOT_TRY
     if (!params || !m || !v || !X || !y || !order || n < 1 || epochs < 0 || batch < 1 || batch > 256 || step0 < 0)
         return fail(PCOT_ERR_INVALID, "bad argument");
     for (int64_t i = 0; i < (int64_t)epochs * n; ++i)
@@ -400,11 +411,13 @@ pcot_status pcot_mlp_train(float* params, float* m, float* v, const float* X, co
     HIP_TRY(hipStreamSynchronize(st));
     if (epoch_loss) memcpy(epoch_loss, el.data(), (size_t)epochs * sizeof(float));
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 // ---------------------------------------------------------------- model ---
 pcot_status pcot_model_train(const pcot_record* records, size_t n, const pcot_train_opts* opts, pcot_model** out,
                              float* final_loss, void* stream) {
+    PCOT_TRY
     if (!records || !out || n < 2 || n > (1u << 24)) return fail(PCOT_ERR_INVALID, "need 2 .. 2^24 records");
     pcot_train_opts o;
     memset(&o, 0, sizeof o);
@@ -471,10 +484,12 @@ pcot_status pcot_model_train(const pcot_record* records, size_t n, const pcot_tr
     if (final_loss) *final_loss = el.back();
     *out = m.release();
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_model_predict_ms(const pcot_model* model, const pcot_record* records, size_t n, float* ms,
                                   void* stream) {
+    PCOT_TRY
     if (!model || !records || !ms) return fail(PCOT_ERR_INVALID, "NULL argument");
     std::vector<float> raw(n * 8), out;
     for (size_t i = 0; i < n; ++i) memcpy(&raw[i * 8], records[i].feat, 8 * sizeof(float));
@@ -482,19 +497,23 @@ pcot_status pcot_model_predict_ms(const pcot_model* model, const pcot_record* re
     if (e != PCOT_OK) return e;
     memcpy(ms, out.data(), n * sizeof(float));
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_model_predict(const pcot_model* model, const pcot_problem* prob, uint32_t sched_mask,
                                pcot_tile* best, int32_t* best_sched, double* pred_ms, void* stream) {
+    PCOT_TRY
     pcot_tune_opts o;
     memset(&o, 0, sizeof o);
     o.mode = PCOT_TUNE_MODEL;
     o.sched_mask = sched_mask;
     o.model = model;
     return pcot_tune(prob, &o, best, best_sched, pred_ms, nullptr, 0, nullptr, stream);
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_model_save(const pcot_model* m, const char* path) {
+    PCOT_TRY
     if (!m || !path) return fail(PCOT_ERR_INVALID, "NULL argument");
     FILE* f = fopen(path, "w");
     if (!f) return fail(PCOT_ERR_INVALID, "cannot write %s", path);
@@ -505,9 +524,11 @@ pcot_status pcot_model_save(const pcot_model* m, const char* path) {
     for (int i = 0; i < MLP_NP; ++i) fprintf(f, "%.9g\n", m->params[i]);
     const bool ok = fclose(f) == 0;
     return ok ? PCOT_OK : fail(PCOT_ERR_INVALID, "write error on %s", path);
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 pcot_status pcot_model_load(const char* path, pcot_model** out) {
+    PCOT_TRY
     if (!path || !out) return fail(PCOT_ERR_INVALID, "NULL argument");
     FILE* f = fopen(path, "r");
     if (!f) return fail(PCOT_ERR_INVALID, "cannot read %s", path);
@@ -524,6 +545,7 @@ pcot_status pcot_model_load(const char* path, pcot_model** out) {
     if (!ok) return fail(PCOT_ERR_INVALID, "%s is not a pcot model file", path);
     *out = m.release();
     return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
 }
 
 void pcot_model_free(pcot_model* m) { delete m; }

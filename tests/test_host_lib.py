@@ -82,3 +82,68 @@ def test_planner_full_size_leaf_counts():
         want += k * k
     assert got == want
     assert len(pc.plan("jacobi2d", (n, n), T, (bt, bs, bs), "cot_par")) == want
+
+
+# Fields the tiled executors cannot address (32-bit byte offsets, stores
+# masked at offset 0x7FFFFFF0) are refused on the host; nothing here touches
+# a GPU: validation fails before any pointer is used.
+@pytest.mark.parametrize("kind,dtype,dims", [
+    ("jacobi2d", "f64", (16400, 16400)),     # 2.0 GiB
+    ("heat3d", "f64", (700, 700, 700)),      # 2.6 GiB
+    ("jacobi2d", "f32", (40000, 40000)),     # 6.0 GiB (past 4 GiB: a 32-bit size would wrap)
+    ("jacobi1d", "bf16", (1 << 30,)),        # 2 GiB of bf16
+])
+def test_tiled_fields_past_the_offset_limit_are_refused(kind, dtype, dims):
+    import paper_1802_00166_amd as pc
+    tile = {"jacobi1d": (16, 256), "jacobi2d": (16, 64, 256), "heat3d": (2, 64, 16, 64)}[kind]
+    tp = pc.make_tile(*tile)
+    for sched in ("slt_lex", "slt_wave", "cot_seq", "cot_par"):
+        n = pc.pcot_stencil_workspace(pc.KINDS[kind], pc.DTYPES[dtype], pc._dims(dims), 8,
+                                      ctypes.byref(tp), pc.SCHEDULES[sched])
+        assert n == 0
+        assert "0x7FFFFFF0" in pc.last_error() or "below" in pc.last_error()
+        st = pc.pcot_stencil_run(pc.KINDS[kind], pc.DTYPES[dtype], pc._dims(dims), 8, ctypes.byref(tp),
+                                 pc.SCHEDULES[sched], ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
+                                 ctypes.c_void_p(0x3000), ctypes.c_size_t(1 << 40), None)
+        assert st == -2  # PCOT_ERR_UNSUPPORTED, before any device work
+    # the batched form validates every instance the same way
+    dims3 = (ctypes.c_int64 * 3)(*(list(dims) + [0] * (3 - len(dims))))
+    Ts = (ctypes.c_int64 * 1)(8)
+    tiles = (pc.pcot_tile * 1)(tp)
+    assert pc.pcot_stencil_workspace_batched(pc.KINDS[kind], pc.DTYPES[dtype], 1, dims3, Ts, tiles,
+                                             pc.SLT_WAVE) == 0
+    # the untiled schedule has no such limit
+    assert pc.pcot_stencil_workspace(pc.KINDS[kind], pc.DTYPES[dtype], pc._dims(dims), 8, None, pc.NAIVE) > 0
+
+
+def test_tiled_field_just_under_the_offset_limit_is_accepted():
+    import paper_1802_00166_amd as pc
+    # f64 16000^2 = 1.91 GiB (+ two rows + 4 KiB) < 0x7FFFFFF0
+    assert pc.workspace_bytes("jacobi2d", "f64", (16000, 16000), 8, (16, 64, 256), "slt_wave") > 0
+    # the largest benchmark field, Heat-3D 512^3 f64 (1 GiB)
+    assert pc.workspace_bytes("heat3d", "f64", (512, 512, 512), 128, (2, 64, 16, 64), "slt_wave") > 0
+    with pytest.raises(pc.PcotError):
+        pc.workspace_bytes("jacobi2d", "f64", (16400, 16400), 8, (16, 64, 256), "slt_wave")
+
+
+def test_dp_plan_item_count_limit():
+    import paper_1802_00166_amd as pc
+    # N = 65536 at b = 32, k-chunk 16: about 2.9e9 k-chunk items, past int offsets
+    tp = pc.make_tile(0, 32, 32, 16)
+    assert pc.pcot_dp_workspace(65536, ctypes.byref(tp), pc.SLT_WAVE) == 0
+    assert "items" in pc.last_error()
+    # the same N with larger chunks stays under the limit (workspace only: no plan is built)
+    tp = pc.make_tile(0, 64, 64, 256)
+    assert pc.pcot_dp_workspace(65536, ctypes.byref(tp), pc.SLT_WAVE) > 0
+
+
+def test_planner_matches_hand_enumerated_2d_orders():
+    """The product planner against the hand-enumerated 2D golden (no oracle in between)."""
+    import json
+    import paper_1802_00166_amd as pc
+    with open(os.path.join(ROOT, "tests", "golden", "cot_order_2d.json")) as f:
+        g = json.load(f)
+    pr = g["problem"]
+    for sched in ("slt_lex", "slt_wave", "cot_seq", "cot_par"):
+        got = pc.plan("jacobi2d", tuple(pr["dims"]), pr["T"], tuple(pr["tile"]), sched)
+        assert [list(k) for k in got] == g[sched], sched

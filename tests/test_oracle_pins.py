@@ -351,3 +351,69 @@ def test_adam_first_step_closed_form():
         want = P[k] - 1e-2 * G[k] / (np.abs(G[k]) + 1e-8)
         assert np.allclose(newp[k], want, rtol=0, atol=1e-12)
         assert np.allclose(m[k], 0.1 * G[k]) and np.allclose(v[k], 0.001 * G[k] ** 2)
+
+
+# Hand-enumerated 2D orders (tests/golden/cot_order_2d.json): a problem in
+# which the recursive order differs from the lexicographic one, the parallel
+# grouping differs from the sequential one, and both wrong bit orders (and a
+# concatenating merge) give other sequences, so each of those mistakes in the
+# oracle fails here.
+def _cot2d():
+    with open(os.path.join(GOLD, "cot_order_2d.json")) as f:
+        return json.load(f)
+
+
+def test_cot_order_2d_hand_enumeration():
+    g = _cot2d()
+    pr = g["problem"]
+    dims, T, tile = tuple(pr["dims"]), pr["T"], tuple(pr["tile"])
+    got = {
+        "slt_lex": oracle.slt_leaves(dims, T, tile),
+        "slt_wave": oracle.slt_leaves(dims, T, tile, wavefront=True),
+        "cot_seq": oracle.cot_leaves(dims, T, tile),
+        "cot_par": oracle.cot_leaves(dims, T, tile, parallel_groups=True),
+    }
+    for name, order in got.items():
+        assert [list(k) for k in order] == g[name], name
+        assert oracle.check_plan(order, dims, T, tile) == [], name
+
+
+def test_cot_order_2d_golden_discriminates():
+    g = _cot2d()
+    seqs = [g["slt_lex"], g["slt_wave"], g["cot_seq"], g["cot_par"]]
+    assert len({json.dumps(s) for s in seqs}) == 4
+    for name, w in g["wrong"].items():
+        assert sorted(map(tuple, w)) == sorted(map(tuple, g["cot_seq"])), name
+        if name.startswith("cot_seq"):
+            assert w != g["cot_seq"], name
+        else:
+            assert w != g["cot_par"], name
+    # the wrong orders are still legal visiting orders: only the golden tells them apart
+    pr = g["problem"]
+    for name, w in g["wrong"].items():
+        assert oracle.check_plan([tuple(k) for k in w], tuple(pr["dims"]), pr["T"], tuple(pr["tile"])) == [], name
+
+
+def _mlp_golden_params(g):
+    P = {k: np.zeros(s) for k, s in oracle.MLP_SHAPES}
+    for name in ("W1", "W2"):
+        for key, v in g[name].items():
+            i, j = (int(t) for t in key.split(","))
+            P[name][i, j] = v
+    for name in ("b1", "b2"):
+        for key, v in g[name].items():
+            P[name][int(key)] = v
+    for key, v in g["W3"].items():
+        P["W3"][0, int(key)] = v
+    P["b3"][0] = g["b3"]
+    return P
+
+
+def test_mlp_forward_hand_computed_value():
+    with open(os.path.join(GOLD, "mlp_forward.json")) as f:
+        g = json.load(f)
+    P = _mlp_golden_params(g)
+    yhat, _ = oracle.mlp_forward(P, np.array(g["X"], dtype=np.float64))
+    assert list(yhat) == g["expected"]
+    for name, w in g["wrong"].items():
+        assert w != g["expected"], name
