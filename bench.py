@@ -126,20 +126,48 @@ def measure_copy_gbs(torch, reps=5):
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
+def host_info():
+    """Host CPU model, logical CPU count and the oracle's compiler and flags."""
+    import platform
+    import subprocess
+    import oracle
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cc = subprocess.run(["gcc", "--version"], stdout=subprocess.PIPE, text=True).stdout.splitlines()[0]
+    except (OSError, IndexError):
+        cc = "gcc"
+    return {"nproc": os.cpu_count(), "cpu_model": model, "compiler": cc, "flags": " ".join(oracle.CFLAGS)}
+
+
 def cpu_baseline(u0, sample_T=T):
     """Oracle on the host: the full 4096^2 field for `sample_T` steps (by
-    default the whole job), on up to 16 host threads (the threaded oracle
-    gives the single-thread oracle's bits)."""
+    default the whole job).  `value` is the single-thread oracle (the binding
+    one); `all_cores` is the same source on up to 16 OpenMP threads (same bits:
+    the threads split the outer loop of each step)."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    oracle.stencil("jacobi2d", "f64", u0[:64, :64], 1, threads=threads)  # load/build
+    oracle.stencil("jacobi2d", "f64", u0[:64, :64], 1)  # load/build
+    upd = (NY - 2) * (NX - 2) * sample_T
+    t0 = time.perf_counter()
+    oracle.stencil("jacobi2d", "f64", u0, sample_T, threads=1)
+    dt1 = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.stencil("jacobi2d", "f64", u0, sample_T, threads=threads)
-    dt = time.perf_counter() - t0
-    upd = (NY - 2) * (NX - 2) * sample_T
-    return {"value": round(upd / dt / 1e9, 4), "unit": "GUpdates/s", "cores": threads, "kind": "oracle",
-            "sample": "Jacobi-2D 4096^2 f64, %d of the 512 steps, plain C loop nest, %d OpenMP threads, %.2f s"
-                      % (sample_T, threads, dt)}
+    dtn = time.perf_counter() - t0
+    rec = {"value": round(upd / dt1 / 1e9, 4), "unit": "GUpdates/s", "cores": 1, "kind": "oracle",
+           "sample": "Jacobi-2D 4096^2 f64, %d of the 512 steps, plain C loop nest, 1 thread, %.2f s"
+                     % (sample_T, dt1),
+           "all_cores": {"value": round(upd / dtn / 1e9, 4), "cores": threads, "seconds": round(dtn, 3)}}
+    rec.update(host_info())
+    return rec
 
 
 def pick_tiles():
@@ -385,27 +413,9 @@ def workload_batched(args, pc, torch):
     shapes = [(ny, nx) for (ny, nx, _) in inst]
     upd = sum((ny - 2) * (nx - 2) * TT for (ny, nx, TT) in inst)
     model = tune.load_default_model()
-    uniform = [(16, 64, 128), (32, 64, 128), (16, 64, 256), (32, 64, 256), (16, 32, 128), (32, 32, 256),
-               (16, 128, 256), (64, 64, 128)]
-    choice = {"uniform_%d_%d_%d" % t: [t] * len(inst) for t in uniform}
+    choice = {"uniform_%d_%d_%d" % t: [t] * len(inst) for t in tune.BATCH_UNIFORM_TILES}
     if model is not None:
-        # one b_x for the whole batch (one executor instance): per instance
-        # the best predicted SLT_WAVE candidate of each b_x, then the b_x with
-        # the smallest predicted total
-        per = []
-        for sh, TT in zip(shapes, Ts):
-            prob = tune.problem("jacobi2d", "f32", sh, TT)
-            cands = [c for c in tune.candidates(prob, ["slt_wave"])]
-            ms = model.predict_ms([{"feat": list(tune.features(prob, c[0], c[1])), "tile": list(c[0]),
-                                    "schedule": c[1]} for c in cands])
-            best = {}
-            for c, m in zip(cands, ms):
-                bxc = c[0][2]
-                if bxc not in best or m < best[bxc][1]:
-                    best[bxc] = (tuple(c[0]), m)
-            per.append(best)
-        bx = min((64, 128, 256), key=lambda b: sum(p[b][1] for p in per))
-        choice["model"] = [p[bx][0] for p in per]
+        choice["model"] = tune.batch_model_tiles(model, "jacobi2d", "f32", shapes, Ts)
     results = {}
     for name, tiles in choice.items():
         outs = [torch.empty_like(x) for x in xs]
@@ -645,7 +655,7 @@ def main():
         r["copy_gbs"] = round(cg, 1)
         if r.get("unit") == "GB/s":
             r["frac_of_copy"] = round(r["achieved"] / cg, 4)
-        rec["cpu_baseline"] = cpu_baseline(u0)
+        rec["cpu_baseline"] = cpu_baseline(u0, 128)
     print(json.dumps(rec), flush=True)
 
 

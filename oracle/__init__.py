@@ -33,12 +33,14 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _lib = None
 
 
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
+
+
 def build(force: bool = False) -> str:
     """Compile oracle.c with gcc (IEEE doubles via SSE2, no FMA contraction, OpenMP)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc"] + CFLAGS + ["-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _SO)
     return _SO

@@ -230,3 +230,32 @@ def load_sweep_best(kind: str, dtype: str, shape, T: int):
     if not e:
         return None
     return tuple(e["best_tile"]), e["best_schedule"], e["best_ms"]
+
+
+# Uniform tiles the batched launch is compared over (one tile for every
+# instance); one executor instance runs a batch, so b_x is shared.
+BATCH_UNIFORM_TILES = [(16, 64, 128), (32, 64, 128), (16, 64, 256), (32, 64, 256), (16, 32, 128),
+                       (32, 32, 256), (16, 128, 256), (64, 64, 128)]
+
+
+def batch_model_tiles(model: Model, kind: str, dtype: str, shapes, Ts, schedule: str = "slt_wave"):
+    """Per-instance tiles of a batch from the cost model.  The batch runs one
+    executor instance, so b_x is common: per instance the best predicted
+    candidate of each b_x, then the b_x with the smallest predicted total."""
+    per = []
+    for sh, TT in zip(shapes, Ts):
+        prob = problem(kind, dtype, sh, TT)
+        cands = list(candidates(prob, [schedule]))
+        ms = model.predict_ms([{"feat": list(features(prob, c[0], c[1])), "tile": list(c[0]),
+                                "schedule": c[1]} for c in cands])
+        best = {}
+        for c, m in zip(cands, ms):
+            bxc = c[0][-1]
+            if bxc not in best or m < best[bxc][1]:
+                best[bxc] = (tuple(c[0]), m)
+        per.append(best)
+    common = set(per[0])
+    for p in per[1:]:
+        common &= set(p)
+    bx = min(sorted(common), key=lambda b: sum(p[b][1] for p in per))
+    return [p[bx][0] for p in per]
