@@ -155,6 +155,23 @@ int64_t pcot_stencil_plan(int32_t kind, const int64_t* dims, int64_t T, const pc
 pcot_status pcot_error_norms(int32_t dtype, int32_t d, const int64_t* dims, const void* x,
                              const double* r, double* out, void* stream);
 
+/* Allocation-free variant of pcot_error_norms, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same two reduction passes, same bits.
+ *   x, r   device, as in pcot_error_norms.
+ *   out    DEVICE, 4 doubles: max|x-r|, max|r|, sum (x-r)^2, sum r^2.
+ * The first pass's partial sums live in a static device array of the
+ * library (1024 x 4 doubles = 32 KiB per GPU, held until the process ends;
+ * its address is looked up once per device on the first call).  Every call
+ * rewrites all of it, so no clearing is needed; calls that overlap on one
+ * GPU (different streams, no ordering between them) race on it.  Only
+ * enqueues: no synchronisation, no hipMalloc / hipFree, no host-device copy.
+ * Inputs with more than PCOT_NORMS_STATIC_MAX_POINTS interior points return
+ * PCOT_ERR_UNSUPPORTED. */
+#define PCOT_NORMS_STATIC_MAX_POINTS (1LL << 36)
+pcot_status pcot_error_norms_static(int32_t dtype, int32_t d, const int64_t* dims, const void* x,
+                                    const double* r, double* out, void* stream);
+
 /* --------------------------------------------------------- interval DP --- */
 
 /* Matrix-chain / optimal parenthesization (the interval DP of the paper's OSP

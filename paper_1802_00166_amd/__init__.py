@@ -87,6 +87,7 @@ _SIGS = {
     "pcot_stencil_run_batched": (_I32, [_I32, _I32, _I32, _I64P, _I64P, _TP, _I32, ctypes.POINTER(_P),
                                         ctypes.POINTER(_P), _P, _SZ, _P]),
     "pcot_error_norms": (_I32, [_I32, _I32, _I64P, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "pcot_error_norms_static": (_I32, [_I32, _I32, _I64P, _P, _P, _P, _P]),
     "pcot_tune_candidates": (_I64, [ctypes.POINTER(pcot_problem), ctypes.c_uint32, _TP,
                                     ctypes.POINTER(ctypes.c_int32), _I64]),
     "pcot_features": (_I32, [ctypes.POINTER(pcot_problem), _TP, _I32, ctypes.POINTER(ctypes.c_float)]),
@@ -254,6 +255,17 @@ def error_norms(dtype: str, x, r, stream=None) -> dict:
     return {"max_abs": max_abs, "max_ref": max_ref, "sum_sq": sse, "sum_ref_sq": ssr,
             "max_rel": max_abs / max_ref if max_ref > 0 else float("nan"),
             "l2_rel": (sse / ssr) ** 0.5 if ssr > 0 else float("nan")}
+
+
+def error_norms_static(dtype: str, x, r, out, stream=None) -> None:
+    """Allocation-free norms: enqueues the reduction, the four values land in
+    `out` (a float64 device tensor of 4); no synchronisation."""
+    torch = _torch()
+    assert r.dtype == torch.float64 and r.shape == x.shape and r.is_contiguous() and x.is_contiguous()
+    assert out.dtype == torch.float64 and out.numel() >= 4 and out.is_cuda
+    check(pcot_error_norms_static(DTYPES[dtype], x.dim(), _dims(x.shape), ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  stream_ptr(stream)))
 
 
 def stream_status(workspace, stream=None) -> int:

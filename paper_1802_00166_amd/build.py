@@ -45,12 +45,27 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+def _includes(path: str, seen=None) -> set:
+    """Local headers a source includes, followed transitively."""
+    import re
+    seen = set() if seen is None else seen
+    with open(path) as f:
+        for name in re.findall(r'^#include "([^"]+)"', f.read(), re.M):
+            for d in (os.path.dirname(path), CSRC, os.path.join(ROOT, "include")):
+                p = os.path.join(d, name)
+                if os.path.exists(p) and p not in seen:
+                    seen.add(p)
+                    _includes(p, seen)
+                    break
+    return seen
+
+
 def _stale(src: str) -> bool:
-    """Object missing or older than its source or any header of csrc/include."""
+    """Object missing or older than its source or any header it includes."""
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if not os.path.exists(obj):
         return True
-    deps = [src] + glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    deps = [src] + sorted(_includes(src))
     return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
 
 

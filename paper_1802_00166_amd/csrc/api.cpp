@@ -824,6 +824,28 @@ pcot_status pcot_error_norms(int32_t dtype, int32_t d, const int64_t* dims, cons
     PCOT_CATCH(PCOT_ERR_HOST)
 }
 
+pcot_status pcot_error_norms_static(int32_t dtype, int32_t d, const int64_t* dims, const void* x,
+                                    const double* r, double* out, void* stream) {
+    PCOT_TRY
+    if (dtype < PCOT_F64 || dtype > PCOT_BF16) return fail(PCOT_ERR_INVALID, "unknown dtype %d", dtype);
+    if (d < 1 || d > 3) return fail(PCOT_ERR_INVALID, "d=%d (need 1..3)", d);
+    if (!dims || !x || !r || !out) return fail(PCOT_ERR_INVALID, "NULL argument");
+    int64_t n[3] = {1, 1, 1};
+    for (int i = 0; i < d; ++i) {
+        if (dims[i] < 3 || dims[i] > (1LL << 30)) return fail(PCOT_ERR_INVALID, "dims[%d]=%lld", i, (long long)dims[i]);
+        n[i] = dims[i];
+    }
+    const double total = (double)(n[0] - 2) * (double)(d >= 2 ? n[1] - 2 : 1) * (double)(d >= 3 ? n[2] - 2 : 1);
+    if (total > (double)PCOT_NORMS_STATIC_MAX_POINTS)
+        return fail(PCOT_ERR_UNSUPPORTED, "%.0f interior points exceed the allocation-free limit %lld", total,
+                    (long long)PCOT_NORMS_STATIC_MAX_POINTS);
+    double* scratch = nullptr;
+    HIP_TRY(norms_static_scratch(&scratch));
+    HIP_TRY(launch_norms_to(dtype, d, n, x, r, scratch, out, (hipStream_t)stream));
+    return PCOT_OK;
+    PCOT_CATCH(PCOT_ERR_HOST)
+}
+
 size_t pcot_dp_workspace(int64_t N, const pcot_tile* tile, int32_t schedule) {
     PCOT_TRY
     DPArgs A;

@@ -61,6 +61,13 @@ hipError_t launch_copy_boundary_batched(int dtype, const TiledProblem* probs, in
 // Error norms (binary64): `scratch` holds norms_scratch_bytes(); the four
 // results land at the end of it.
 size_t norms_scratch_bytes();
+// Same two passes with the final four values written to `result` (device).
+hipError_t launch_norms_to(int dtype, int d, const int64_t* n, const void* x, const double* r, double* scratch,
+                           double* result, hipStream_t s);
+// Device address of the library's static partials array on the current
+// device (looked up once per device); its size in bytes.
+hipError_t norms_static_scratch(double** out);
+size_t norms_static_scratch_bytes();
 hipError_t launch_norms(int dtype, int d, const int64_t* n, const void* x, const double* r, double* scratch,
                         hipStream_t s);
 

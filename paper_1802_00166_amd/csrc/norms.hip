@@ -4,6 +4,8 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <mutex>
+
 namespace pcot {
 
 namespace {
@@ -81,6 +83,11 @@ size_t norms_scratch_bytes() { return (size_t)(NG * 4 + 4) * sizeof(double); }
 
 hipError_t launch_norms(int dtype, int d, const int64_t* n, const void* x, const double* r, double* scratch,
                         hipStream_t s) {
+    return launch_norms_to(dtype, d, n, x, r, scratch, scratch + NG * 4, s);
+}
+
+hipError_t launch_norms_to(int dtype, int d, const int64_t* n, const void* x, const double* r, double* scratch,
+                           double* result, hipStream_t s) {
     const long long n0 = n[0], n1 = d >= 2 ? n[1] : 1, n2 = d >= 3 ? n[2] : 1;
     switch (dtype) {
         case 0: hipLaunchKernelGGL(k_norms_pass1<double>, dim3(NG), dim3(NB), 0, s, (const double*)x, r, d, n0, n1, n2, scratch); break;
@@ -89,8 +96,37 @@ hipError_t launch_norms(int dtype, int d, const int64_t* n, const void* x, const
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_norms_pass2, dim3(1), dim3(NB), 0, s, scratch, scratch + NG * 4);
+    hipLaunchKernelGGL(k_norms_pass2, dim3(1), dim3(NB), 0, s, scratch, result);
     return hipGetLastError();
+}
+
+// Allocation-free variant's scratch: the first pass's partials (NG blocks x 4
+// values, every slot rewritten by every call, so nothing needs clearing).
+// One copy per GPU, held until the process ends.  Its host-side name is not a
+// device address: host code uses the address looked up per device below.
+__device__ __align__(256) double scratch[NG * 4];
+namespace {
+constexpr int MAX_DEV = 64;
+std::mutex g_static_mu;
+double* g_static_ptr[MAX_DEV] = {};
+}  // namespace
+
+size_t norms_static_scratch_bytes() { return sizeof(double) * NG * 4; }
+
+hipError_t norms_static_scratch(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_static_ptr[dev] = (double*)p;
+    }
+    *out = g_static_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace pcot
