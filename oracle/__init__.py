@@ -7,11 +7,15 @@ fail loudly when its HIP library is missing instead of falling back here.
 Contents
   * stencils (Jacobi-1D/2D, Heat-3D; f64, f32, bf16 storage), matrix-chain DP
     and single-point stencil evaluation: plain C in oracle.c, called via ctypes;
+  * gs2d (in-place Gauss-Seidel, lexicographic order) and fdtd2d (the
+    three-statement 2D Yee update in program order): plain C in oracle.c;
   * chain_brute: enumerates every full bracketing (no DP table);
   * cot_leaves / slt_leaves: the paper's leaf enumerations written from its
     description (bounding box, padding to b*2^k, recursive halving into
     orthants, zero- and empty-orthant early exits);
   * check_plan: brute-force coverage and dependence-order check of a tile list;
+  * check_trap_plan: the same for concurrent-start trapezoid plans (coverage
+    of every step, transitive predecessors of every input, footprints);
   * mlp_*: the 8-64-64-1 ReLU cost model (forward, backward, Adam) in float64.
 
 Parity pins for each function live in tests/test_oracle_pins.py.  The cost
@@ -61,6 +65,7 @@ def _load():
             ("oracle_heat3d_f64", [P, P, I, I, I, I]), ("oracle_heat3d_f32", [P, P, I, I, I, I]),
             ("oracle_heat3d_bf16", [P, P, I, I, I, I]),
             ("oracle_matrix_chain", [P, I, P, P]),
+            ("oracle_gs2d_f64", [P, P, I, I, I]), ("oracle_fdtd2d_f64", [P, P, P, I, I, I]),
         ]:
             f = getattr(lib, name)
             f.argtypes = argt
@@ -113,6 +118,28 @@ def stencil(kind: str, dtype: str, u0: np.ndarray, T: int, threads: int = 1) -> 
     if rc != 0:
         raise MemoryError("oracle allocation failed")
     return out
+
+
+def gs2d(u0: np.ndarray, T: int) -> np.ndarray:
+    """T in-place Gauss-Seidel sweeps (lexicographic order) of the 5-point
+    average, f64, boundary fixed (oracle.c: oracle_gs2d_f64)."""
+    a = np.ascontiguousarray(u0, dtype=np.float64)
+    out = np.empty_like(a)
+    assert a.ndim == 2
+    _load().oracle_gs2d_f64(_ptr(a), _ptr(out), a.shape[0], a.shape[1], int(T))
+    return out
+
+
+FDTD_CE, FDTD_CH = 0.25, 0.5
+
+
+def fdtd2d(ex: np.ndarray, ey: np.ndarray, hz: np.ndarray, T: int):
+    """T steps of the three-statement 2D Yee update (oracle.c:
+    oracle_fdtd2d_f64); returns new (ex, ey, hz), inputs untouched."""
+    e1, e2, h = (np.array(v, dtype=np.float64, order="C", copy=True) for v in (ex, ey, hz))
+    assert e1.shape == e2.shape == h.shape and e1.ndim == 2
+    _load().oracle_fdtd2d_f64(_ptr(e1), _ptr(e2), _ptr(h), e1.shape[0], e1.shape[1], int(T))
+    return e1, e2, h
 
 
 def jacobi2d_point(u0: np.ndarray, T: int, y: int, x: int) -> float:
@@ -323,6 +350,66 @@ def check_plan(order, dims, T, tile):
     for k in pos:
         if k not in seen:
             problems.append(("empty", k))
+    return problems
+
+
+def check_trap_plan(dims, T, tiles, edges, footprint):
+    """Brute-force legality check of a concurrent-start (trapezoid) plan of
+    the 2D radius-1 stencil, from the definition of a legal tiled execution.
+
+    `tiles`: rows (lo_y, hi_y, slo_y, shi_y, fo_y, lo_x, hi_x, slo_x, shi_x,
+    fo_x, t0, nt) in queue order; level l of a tile computes time step t0 + l
+    over [lo + slo*l, hi + shi*l) per axis, cut to the interior.  `edges`:
+    (predecessor, successor) pairs.  Checks, over every point of the
+    iteration space: each interior point of each step is computed by exactly
+    one tile; every edge goes forward in the queue; every input of a point
+    (the point itself and its four neighbours one step earlier, interior
+    only: boundary cells never change) is computed by the same tile or by a
+    transitive predecessor; and each tile's inputs lie inside its register
+    footprint [fo, fo + F).  Returns a list of problems (empty when legal).
+    """
+    ny, nx = dims
+    problems = []
+    owner = np.full((T, ny, nx), -1, dtype=np.int64)
+    for i, t in enumerate(tiles):
+        lo_y, hi_y, slo_y, shi_y, fo_y, lo_x, hi_x, slo_x, shi_x, fo_x, t0, nt = (int(v) for v in t)
+        for l in range(nt):
+            ya, yb = max(lo_y + slo_y * l, 1), min(hi_y + shi_y * l, ny - 1)
+            xa, xb = max(lo_x + slo_x * l, 1), min(hi_x + shi_x * l, nx - 1)
+            if ya >= yb or xa >= xb:
+                continue
+            if ya - 1 < fo_y or yb + 1 > fo_y + footprint[0] or xa - 1 < fo_x or xb + 1 > fo_x + footprint[1]:
+                problems.append(("footprint", i, l))
+            blk = owner[t0 + l, ya:yb, xa:xb]
+            if (blk >= 0).any():
+                problems.append(("overlap", i, l))
+            blk[...] = i
+    if (owner[:, 1:ny - 1, 1:nx - 1] < 0).any():
+        problems.append(("uncovered", int((owner[:, 1:ny - 1, 1:nx - 1] < 0).sum())))
+        return problems
+    n = len(tiles)
+    preds = [[] for _ in range(n)]
+    for a, b in edges:
+        if not a < b:
+            problems.append(("edge order", int(a), int(b)))
+        preds[int(b)].append(int(a))
+    reach = [0] * n  # bitset of transitive predecessors (queue order is topological)
+    for i in range(n):
+        r = 0
+        for a in preds[i]:
+            r |= reach[a] | (1 << a)
+        reach[i] = r
+    sink = owner[1:, 1:ny - 1, 1:nx - 1]
+    pairs = set()
+    for dy, dx in ((0, 0), (-1, 0), (1, 0), (0, -1), (0, 1)):
+        src = owner[:-1, 1 + dy:ny - 1 + dy, 1 + dx:nx - 1 + dx]
+        # boundary cells (never computed) carry -1 and need no producer
+        m = (src >= 0) & (src != sink)
+        if m.any():
+            pairs.update(zip(src[m].tolist(), sink[m].tolist()))
+    for a, b in pairs:
+        if not (reach[b] >> a) & 1:
+            problems.append(("dependence", a, b))
     return problems
 
 

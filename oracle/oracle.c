@@ -329,3 +329,48 @@ int oracle_matrix_chain(const int64_t* p, int64_t N, int64_t* C, int64_t* split)
     free(CT);
     return 0;
 }
+
+/* ---------------------------------------------------- Gauss-Seidel-2D --- */
+/* In-place Gauss-Seidel sweeps of the 5-point average over the interior, in
+ * lexicographic order (rows outer, columns inner): each point is replaced
+ * by 0.2*((((c + n) + s) + e) + w) where n and w already hold this sweep's
+ * values and c, s, e the previous sweep's.  The dependence inside a time
+ * step is what separates it from Jacobi (Section 6.2 discussion of
+ * Gauss-Seidel style stencils; Table 2, GS-2D). */
+int oracle_gs2d_f64(const double* in, double* out, int64_t ny, int64_t nx, int64_t T) {
+    memcpy(out, in, sizeof(double) * ny * nx);
+    for (int64_t t = 0; t < T; ++t)
+        for (int64_t y = 1; y < ny - 1; ++y)
+            for (int64_t x = 1; x < nx - 1; ++x) {
+                double* u = out + y * nx + x;
+                *u = 0.2 * ((((u[0] + u[-nx]) + u[nx]) + u[1]) + u[-1]);
+            }
+    return 0;
+}
+
+/* ---------------------------------------------------------- FDTD-2D --- */
+/* Three-statement time loop (an imperfect nest: three loop nests inside the
+ * time loop; Section 4.4, Table 2 FDTD-2D), the 2D transverse-electric Yee
+ * scheme on fields ex, ey, hz of ny x nx cells, updated in place:
+ *   ey[i][j] -= CE * (hz[i][j] - hz[i-1][j])                     1 <= i < ny,  0 <= j < nx
+ *   ex[i][j] += CE * (hz[i][j] - hz[i][j-1])                     0 <= i < ny,  1 <= j < nx
+ *   hz[i][j] -= CH * ((ey[i+1][j] - ey[i][j]) - (ex[i][j+1] - ex[i][j]))
+ *                                                                0 <= i < ny-1, 0 <= j < nx-1
+ * Cells outside those ranges keep their values (fixed edges). */
+#define FDTD_CE 0.25
+#define FDTD_CH 0.5
+int oracle_fdtd2d_f64(double* ex, double* ey, double* hz, int64_t ny, int64_t nx, int64_t T) {
+    for (int64_t t = 0; t < T; ++t) {
+        for (int64_t i = 1; i < ny; ++i)
+            for (int64_t j = 0; j < nx; ++j)
+                ey[i * nx + j] = ey[i * nx + j] - FDTD_CE * (hz[i * nx + j] - hz[(i - 1) * nx + j]);
+        for (int64_t i = 0; i < ny; ++i)
+            for (int64_t j = 1; j < nx; ++j)
+                ex[i * nx + j] = ex[i * nx + j] + FDTD_CE * (hz[i * nx + j] - hz[i * nx + j - 1]);
+        for (int64_t i = 0; i < ny - 1; ++i)
+            for (int64_t j = 0; j < nx - 1; ++j)
+                hz[i * nx + j] = hz[i * nx + j] - FDTD_CH * ((ey[(i + 1) * nx + j] - ey[i * nx + j]) -
+                                                             (ex[i * nx + j + 1] - ex[i * nx + j]));
+    }
+    return 0;
+}

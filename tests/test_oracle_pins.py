@@ -417,3 +417,121 @@ def test_mlp_forward_hand_computed_value():
     assert list(yhat) == g["expected"]
     for name, w in g["wrong"].items():
         assert w != g["expected"], name
+
+
+# ------------------------------------------------------- Gauss-Seidel-2D ---
+def _gs_single_assignment(u0, T):
+    """Time-expanded form: v[t][i][j] from v[t-1] (c, s, e) and v[t] (n, w),
+    one array per step, no in-place update (pure Python, small sizes)."""
+    ny, nx = u0.shape
+    v = [u0.astype(np.float64).copy()]
+    for t in range(1, T + 1):
+        cur = v[t - 1].copy()
+        for i in range(1, ny - 1):
+            for j in range(1, nx - 1):
+                c, n = v[t - 1][i, j], cur[i - 1, j]
+                s, e, w = v[t - 1][i + 1, j], v[t - 1][i, j + 1], cur[i, j - 1]
+                cur[i, j] = 0.2 * ((((c + n) + s) + e) + w)
+        v.append(cur)
+    return v[T]
+
+
+def test_gs2d_equals_single_assignment_form():
+    rng = np.random.default_rng(5)
+    u0 = rng.random((7, 9))
+    assert np.array_equal(oracle.gs2d(u0, 3), _gs_single_assignment(u0, 3))
+
+
+def test_gs2d_linear_integer_field_is_fixed():
+    """A linear field (boundary included) is discrete-harmonic: n + s = e + w
+    = 2c, so 0.2 * 5c = c exactly for integer c; a wrong neighbour breaks it."""
+    i, j = np.mgrid[0:9, 0:11]
+    u0 = (3 + 2 * i + 5 * j).astype(np.float64)
+    assert np.array_equal(oracle.gs2d(u0, 6), u0)
+
+
+def test_gs2d_one_interior_point_is_jacobi():
+    rng = np.random.default_rng(6)
+    u0 = rng.random((3, 3))
+    assert np.array_equal(oracle.gs2d(u0, 4), oracle.stencil("jacobi2d", "f64", u0, 4))
+
+
+def test_gs2d_one_sweep_exact_rationals():
+    """One sweep on a 4x5 grid in exact rational arithmetic (lexicographic,
+    new north and west values): the oracle is within rounding of it, and it
+    is not the Jacobi result."""
+    from fractions import Fraction as Fr
+    vals = [[0, 1, 2, 3, 4], [5, 7, 11, 13, 6], [8, 17, 19, 23, 9], [10, 12, 14, 15, 16]]
+    u = [[Fr(v) for v in row] for row in vals]
+    for i in range(1, 3):
+        for j in range(1, 4):
+            u[i][j] = Fr(1, 5) * (u[i][j] + u[i - 1][j] + u[i + 1][j] + u[i][j + 1] + u[i][j - 1])
+    got = oracle.gs2d(np.array(vals, dtype=np.float64), 1)
+    exact = np.array([[float(v) for v in row] for row in u])
+    assert np.allclose(got, exact, rtol=4e-16, atol=0)
+    jac = oracle.stencil("jacobi2d", "f64", np.array(vals, dtype=np.float64), 1)
+    assert not np.allclose(got[1:3, 1:4], jac[1:3, 1:4])
+
+
+def test_gs2d_restart():
+    rng = np.random.default_rng(7)
+    u0 = rng.random((12, 17))
+    assert np.array_equal(oracle.gs2d(oracle.gs2d(u0, 3), 4), oracle.gs2d(u0, 7))
+
+
+# --------------------------------------------------------------- FDTD-2D ---
+def _fdtd_single_assignment(ex, ey, hz, T):
+    """Time-expanded Yee update: E^t from E^{t-1} and H^{t-1}, then H^t from
+    H^{t-1} and E^t (pure Python loops, one array per field and step)."""
+    ny, nx = hz.shape
+    E1, E2, H = [ex.copy()], [ey.copy()], [hz.copy()]
+    for t in range(1, T + 1):
+        a, b, h = E1[-1].copy(), E2[-1].copy(), H[-1].copy()
+        for i in range(1, ny):
+            for j in range(nx):
+                b[i, j] = E2[-1][i, j] - 0.25 * (H[-1][i, j] - H[-1][i - 1, j])
+        for i in range(ny):
+            for j in range(1, nx):
+                a[i, j] = E1[-1][i, j] + 0.25 * (H[-1][i, j] - H[-1][i, j - 1])
+        for i in range(ny - 1):
+            for j in range(nx - 1):
+                h[i, j] = H[-1][i, j] - 0.5 * ((b[i + 1, j] - b[i, j]) - (a[i, j + 1] - a[i, j]))
+        E1.append(a)
+        E2.append(b)
+        H.append(h)
+    return E1[-1], E2[-1], H[-1]
+
+
+def test_fdtd2d_impulse_golden():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fdtd_impulse.json")) as f:
+        g = json.load(f)
+    shape = tuple(g["shape"])
+    hz = np.zeros(shape)
+    hz[tuple(g["impulse"])] = 1.0
+    ex, ey, h = oracle.fdtd2d(np.zeros(shape), np.zeros(shape), hz, 1)
+    for name, arr in (("hz", h), ("ey", ey), ("ex", ex)):
+        want = np.zeros(shape)
+        for i, j, v in g[name]:
+            want[i, j] = v
+        assert np.array_equal(arr, want), name
+
+
+def test_fdtd2d_equals_single_assignment_form():
+    rng = np.random.default_rng(8)
+    f = [rng.random((6, 8)) - 0.5 for _ in range(3)]
+    got = oracle.fdtd2d(*f, 3)
+    want = _fdtd_single_assignment(*f, 3)
+    for g_, w_ in zip(got, want):
+        assert np.array_equal(g_, w_)
+
+
+def test_fdtd2d_constant_fields_and_restart():
+    c = [np.full((9, 10), v) for v in (0.75, -1.5, 3.0)]
+    for g_, w_ in zip(oracle.fdtd2d(*c, 5), c):
+        assert np.array_equal(g_, w_)
+    rng = np.random.default_rng(9)
+    f = [rng.random((13, 11)) for _ in range(3)]
+    a = oracle.fdtd2d(*oracle.fdtd2d(*f, 2), 3)
+    b = oracle.fdtd2d(*f, 5)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
