@@ -66,6 +66,7 @@ def _load():
             ("oracle_heat3d_bf16", [P, P, I, I, I, I]),
             ("oracle_matrix_chain", [P, I, P, P]),
             ("oracle_gs2d_f64", [P, P, I, I, I]), ("oracle_fdtd2d_f64", [P, P, P, I, I, I]),
+            ("oracle_motiv_f64", [P, P, I, I]),
         ]:
             f = getattr(lib, name)
             f.argtypes = argt
@@ -140,6 +141,59 @@ def fdtd2d(ex: np.ndarray, ey: np.ndarray, hz: np.ndarray, T: int):
     assert e1.shape == e2.shape == h.shape and e1.ndim == 2
     _load().oracle_fdtd2d_f64(_ptr(e1), _ptr(e2), _ptr(h), e1.shape[0], e1.shape[1], int(T))
     return e1, e2, h
+
+
+def motiv(a: np.ndarray, T: int) -> np.ndarray:
+    """The appendix's motivating 1D program run as written, with its
+    two-buffer allocation X[t mod 2] (oracle.c: oracle_motiv_f64): T steps of
+    S1 (interior, reading the left boundary value of the previous step) then
+    S2 / S3 (both boundaries through g).  Returns X after T steps."""
+    x = np.ascontiguousarray(a, dtype=np.float64)
+    assert x.ndim == 1 and x.shape[0] >= 3
+    out = np.empty_like(x)
+    _load().oracle_motiv_f64(_ptr(x), _ptr(out), x.shape[0], int(T))
+    return out
+
+
+def motiv_tiled_order(a: np.ndarray, T: int, bt: int, bx: int, aux: bool = True) -> np.ndarray:
+    """The same program executed tile by tile in a different order: the
+    skewed iteration space (t, j = i + t) cut into bt x bx boxes, visited
+    band by band, left to right; every box runs its points level by level.
+    With aux=True the values of S2 and S3 go to single-assignment arrays
+    Y[t], Z[t] (the appendix's affine split; S1 reads Y[t-1] instead of
+    X[(t-1)%2][0]) and X keeps the two-buffer allocation for S1 only.  With
+    aux=False the original allocation is kept, whose memory-based
+    dependences such an order violates.  Pure Python; small sizes."""
+    N = len(a)
+    X = [np.array(a, dtype=np.float64), np.array(a, dtype=np.float64)]
+    Y = [float(a[0])] + [0.0] * T
+    Z = [float(a[N - 1])] + [0.0] * T
+    f = lambda p, q, r, s: 0.25 * (((p + q) + r) + s)
+    g = lambda y: 0.5 * y + 0.25
+    if aux:
+        for t in range(1, T + 1):  # S2, S3 depend only on themselves
+            Y[t] = g(Y[t - 1])
+            Z[t] = g(Z[t - 1])
+    for t0 in range(1, T + 1, bt):
+        for j0 in range(1 + t0, N - 2 + T + 1, bx):
+            for t in range(t0, min(t0 + bt, T + 1)):
+                cur, old = X[t % 2], X[(t - 1) % 2]
+                for j in range(j0, j0 + bx):
+                    i = j - t
+                    if 1 <= i <= N - 2:
+                        if aux:
+                            left = Y[t - 1] if i == 1 else old[i - 1]
+                            right = Z[t - 1] if i == N - 2 else old[i + 1]
+                            cur[i] = f(left, old[i], right, Y[t - 1])
+                        else:
+                            cur[i] = f(old[i - 1], old[i], old[i + 1], old[0])
+                if not aux and j0 == 1 + t0:   # boundaries updated with the first box of a level
+                    cur[0] = g(old[0])
+                    cur[N - 1] = g(old[N - 1])
+    out = X[T % 2].copy()
+    if aux:
+        out[0], out[N - 1] = Y[T], Z[T]
+    return out
 
 
 def jacobi2d_point(u0: np.ndarray, T: int, y: int, x: int) -> float:

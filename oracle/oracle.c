@@ -374,3 +374,33 @@ int oracle_fdtd2d_f64(double* ex, double* ey, double* hz, int64_t ny, int64_t nx
     }
     return 0;
 }
+
+/* ------------------------------------------------ motivating example --- */
+/* The appendix's motivating 1D program (Memory Allocation, Fig. motiv), with
+ * the two-buffer allocation X[t mod 2][i] of the original code:
+ *   X[0][i] = A[i];
+ *   for t = 1..T: for i = 1..N-2:  X[t%2][i] = f(X[(t-1)%2][i-1], X[(t-1)%2][i],
+ *                                                X[(t-1)%2][i+1], X[(t-1)%2][0])   (S1)
+ *                 X[t%2][0] = g(X[(t-1)%2][0]);  X[t%2][N-1] = g(X[(t-1)%2][N-1])  (S2, S3)
+ *   out[i] = X[T%2][i].
+ * The paper leaves f and g abstract; here
+ *   f(a, b, c, d) = 0.25 * (((a + b) + c) + d),   g(y) = 0.5 * y + 0.25. */
+static inline double motiv_f(double a, double b, double c, double d) { return 0.25 * (((a + b) + c) + d); }
+static inline double motiv_g(double y) { return 0.5 * y + 0.25; }
+
+int oracle_motiv_f64(const double* A, double* out, int64_t N, int64_t T) {
+    double* X = (double*)malloc(sizeof(double) * 2 * N);
+    if (!X) return -1;
+    memcpy(X, A, sizeof(double) * N);
+    memcpy(X + N, A, sizeof(double) * N);
+    for (int64_t t = 1; t <= T; ++t) {
+        double* cur = X + (t % 2) * N;
+        const double* old = X + ((t - 1) % 2) * N;
+        for (int64_t i = 1; i < N - 1; ++i) cur[i] = motiv_f(old[i - 1], old[i], old[i + 1], old[0]);
+        cur[0] = motiv_g(old[0]);
+        cur[N - 1] = motiv_g(old[N - 1]);
+    }
+    memcpy(out, X + (T % 2) * N, sizeof(double) * N);
+    free(X);
+    return 0;
+}

@@ -535,3 +535,48 @@ def test_fdtd2d_constant_fields_and_restart():
     b = oracle.fdtd2d(*f, 5)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+# ------------------------------------- motivating example (appendix, Fig. motiv) ---
+def _motiv_single_assignment(a, T):
+    """Full expansion: one array per time step (no reuse of memory), S1 on
+    the interior from step t-1, S2 / S3 on the two boundaries."""
+    N = len(a)
+    X = [np.array(a, dtype=np.float64)]
+    for t in range(1, T + 1):
+        p = X[-1]
+        cur = np.empty(N)
+        for i in range(1, N - 1):
+            cur[i] = 0.25 * (((p[i - 1] + p[i]) + p[i + 1]) + p[0])
+        cur[0] = 0.5 * p[0] + 0.25
+        cur[N - 1] = 0.5 * p[N - 1] + 0.25
+        X.append(cur)
+    return X[T]
+
+
+def test_motiv_equals_single_assignment_form():
+    a = np.random.default_rng(11).random(23)
+    assert np.array_equal(oracle.motiv(a, 46), _motiv_single_assignment(a, 46))
+
+
+def test_motiv_fixed_point_and_boundary_closed_form():
+    assert np.array_equal(oracle.motiv(np.full(17, 0.5), 34), np.full(17, 0.5))
+    a = np.zeros(9)
+    for T in (1, 2, 5, 30):
+        out = oracle.motiv(a, T)
+        assert out[0] == out[-1] == 0.5 - 0.5 * 2.0 ** -T      # g(y) = y/2 + 1/4 from 0, exact
+
+
+@pytest.mark.parametrize("bt,bx", [(1, 4), (4, 8), (8, 16), (16, 5), (50, 100)])
+def test_motiv_tiled_order_needs_the_auxiliary_arrays(bt, bx):
+    """Tiles of the skewed space in band / left-to-right order give the
+    program's result when S2 and S3 write single-assignment arrays (the
+    appendix's split); with the original allocation the same order breaks the
+    memory-based dependences whenever a band holds more than one level and a
+    level more than one tile."""
+    a = np.random.default_rng(12).random(31)
+    T = 62
+    want = oracle.motiv(a, T)
+    assert np.array_equal(oracle.motiv_tiled_order(a, T, bt, bx, aux=True), want)
+    if bt > 1 and bx + bt < len(a):
+        assert not np.array_equal(oracle.motiv_tiled_order(a, T, bt, bx, aux=False), want)
