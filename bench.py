@@ -34,6 +34,14 @@ DEFAULT_TILE = (16, 64, 256)
 DEFAULT_SCHED = "slt_wave"
 # matrix chain N = 4096: (unused, b, b, k-chunk)
 CHAIN_TILE = (0, 32, 32, 32)
+# Gauss-Seidel-2D and FDTD-2D at the paper's shape (500 steps of 2000^2)
+GS2D_TILE = (16, 64, 64)
+FDTD2D_TILE = (8, 32, 32)
+# the appendix's motivating 1D program, N = 4096, T = 2N
+MOTIV_TILE = (64, 256)
+# concurrent-start schedules of the headline problem: (b_t, F_y, F_x), schedule
+TRAP_CANDIDATES = [((16, 64, 128), "trap"), ((8, 64, 128), "trap"), ((8, 64, 128), "diamond"),
+                   ((8, 32, 128), "trap")]
 # Heat-3D 512^3, T = 128: the tile each storage type is benchmarked with
 HEAT3D_TILES = {"f64": (2, 64, 16, 64), "f32": (4, 32, 8, 64), "bf16": (4, 32, 8, 64)}
 
@@ -285,6 +293,136 @@ def workload_jacobi1d(args, pc, torch):
                    {"workload": "jacobi1d_3pt_4096_T1000_f64", "tile_bt_bx": list(tile), "schedule": sched},
                    _roof(upd, kms / 1e3, 8 * (2.0 / tile[0] + 4.0 / tile[1]), 3,
                          note="the 32 KiB field stays on chip: bound by latency, not by either roof"), cpu)
+
+
+def workload_gs2d(args, pc, torch):
+    """In-place Gauss-Seidel-2D at the paper's GS-2D shape (500 sweeps of
+    2000^2, Table 2), front executor in skewed tiles, wavefront tile order."""
+    import synth
+    n, TT, tile, sched = 2000, 500, GS2D_TILE, "slt_wave"
+    upd = (n - 2) * (n - 2) * TT
+    u0 = synth.jacobi2d_input(n, n)
+    x = torch.from_numpy(u0).to("cuda:0")
+    y = torch.empty_like(x)
+    ws = pc.alloc_workspace(pc.workspace_bytes("gs2d", "f64", (n, n), TT, tile, sched))
+    dt, kms = _timed(pc, torch, lambda: pc.stencil_run("gs2d", "f64", x, TT, tile, sched, out=y, workspace=ws),
+                     args.steps, args.warmup)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        s = 50
+        t0 = time.perf_counter()
+        oracle.gs2d(u0, s)
+        c = time.perf_counter() - t0
+        cpu = {"value": round((n - 2) ** 2 * s / c / 1e9, 4), "unit": "GUpdates/s", "cores": 1, "kind": "oracle",
+               "sample": "%d of the 500 sweeps, single-thread plain C in-place loop nest, %.2f s" % (s, c)}
+    bt, by, bx = tile
+    # each tile reads and writes its footprint once: ~ 2 * 8 * (by + bt)(bx + bt) bytes per bt*by*bx updates
+    bpu = 16.0 * (by + bt) * (bx + bt) / (bt * by * bx)
+    return _record("GUpdates/s, Gauss-Seidel-2D 2000^2 FP64, 500 in-place sweeps (skewed tiles, wavefront order)",
+                   upd / dt / 1e9, "GUpdates/s", args.steps, args.warmup, dt, "f64",
+                   "synthetic: sin(pi x)sin(pi y) + 1e-3*(2U-1) noise (SplitMix64 stream 2), zero boundary",
+                   {"workload": "gs2d_5pt_2000x2000_T500_f64", "tile_bt_by_bx": list(tile), "schedule": sched},
+                   _roof(upd, kms / 1e3, bpu, 5), cpu)
+
+
+def workload_fdtd2d(args, pc, torch):
+    """FDTD-2D (three statements per step, embedded) at the paper's shape
+    (500 steps of 2000^2, Table 2); the untiled three-kernel step beside it."""
+    import numpy as np
+    import synth
+    n, TT, tile, sched = 2000, 500, FDTD2D_TILE, "slt_wave"
+    upd = n * n * TT  # iterations of the embedded nest (three statements each)
+    s = synth.test_rng(23)
+    f = np.stack([synth.uniform_f64(s, n * n, offset=k * n * n).reshape(n, n) - 0.5 for k in range(3)])
+    x = torch.from_numpy(np.ascontiguousarray(f)).to("cuda:0")
+    y = torch.empty_like(x)
+    ws = pc.alloc_workspace(pc.workspace_bytes("fdtd2d", "f64", (n, n), TT, tile, sched))
+    dt, kms = _timed(pc, torch, lambda: pc.stencil_run("fdtd2d", "f64", x, TT, tile, sched, out=y, workspace=ws),
+                     args.steps, args.warmup)
+    wsn = pc.alloc_workspace(pc.workspace_bytes("fdtd2d", "f64", (n, n), TT, None, "naive"))
+    dtn, _ = _timed(pc, torch, lambda: pc.stencil_run("fdtd2d", "f64", x, TT, None, "naive", out=y, workspace=wsn),
+                    max(2, args.steps // 2), 1)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        st = 20
+        t0 = time.perf_counter()
+        oracle.fdtd2d(f[0], f[1], f[2], st)
+        c = time.perf_counter() - t0
+        cpu = {"value": round(n * n * st / c / 1e9, 4), "unit": "GIterations/s", "cores": 1, "kind": "oracle",
+               "sample": "%d of the 500 steps, single-thread plain C three loop nests, %.2f s" % (st, c)}
+    bt, by, bx = tile
+    bpu = 3 * 16.0 * (by + bt) * (bx + bt) / (bt * by * bx)
+    rec = _record("GIterations/s, FDTD-2D 2000^2 FP64, 500 steps (three statements per iteration, embedded nest "
+                  "in skewed tiles, wavefront order)", upd / dt / 1e9, "GIterations/s", args.steps, args.warmup, dt,
+                  "f64", "synthetic: ex, ey, hz uniform[-0.5, 0.5) (SplitMix64 test stream 23)",
+                  {"workload": "fdtd2d_2000x2000_T500_f64", "tile_bt_by_bx": list(tile), "schedule": sched},
+                  _roof(upd, kms / 1e3, bpu, 11), cpu)
+    rec["untiled_three_kernel_step"] = {"ms": round(dtn * 1e3, 3), "giter_s": round(upd / dtn / 1e9, 2)}
+    return rec
+
+
+def workload_motiv1d(args, pc, torch):
+    """The appendix's motivating 1D program, N = 4096, T = 2N, with the
+    schedule-independent allocation (two interior buffers, single-assignment
+    boundary arrays), skewed tiles in wavefront order."""
+    import synth
+    n, TT, tile, sched = 4096, 8192, MOTIV_TILE, "slt_wave"
+    upd = (n - 2) * TT
+    a = synth.uniform_f64(synth.test_rng(77), n)
+    x = torch.from_numpy(a).to("cuda:0")
+    y = torch.empty_like(x)
+    ws = pc.alloc_workspace(pc.workspace_bytes("motiv1d", "f64", (n,), TT, tile, sched))
+    dt, kms = _timed(pc, torch, lambda: pc.stencil_run("motiv1d", "f64", x, TT, tile, sched, out=y, workspace=ws),
+                     args.steps, args.warmup)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.motiv(a, TT)
+        c = time.perf_counter() - t0
+        cpu = {"value": round(upd / c / 1e9, 4), "unit": "GUpdates/s", "cores": 1, "kind": "oracle",
+               "sample": "the whole job, single-thread plain C with the program's own allocation, %.3f s" % c}
+    bt, bx = tile
+    rec = _record("GUpdates/s, motivating 1D program (appendix) N=4096 FP64, T=8192, single-assignment boundary "
+                  "arrays", upd / dt / 1e9, "GUpdates/s", args.steps, args.warmup, dt, "f64",
+                  "synthetic: uniform[0,1) (SplitMix64 test stream 77)",
+                  {"workload": "motiv1d_4096_T8192_f64", "tile_bt_bx": list(tile), "schedule": sched},
+                  _roof(upd, kms / 1e3, 8 * (2.0 / bt + 4.0 / bx), 4,
+                        note="a 32 KiB field over 8192 dependent steps: latency-bound"), cpu)
+    rec["workspace_bytes"] = int(pc.workspace_bytes("motiv1d", "f64", (n,), TT, tile, sched))
+    rec["full_expansion_bytes"] = 8 * n * (TT + 1)
+    return rec
+
+
+def workload_trap(args, pc, torch):
+    """The headline problem under the concurrent-start schedules (trapezoid
+    hyperspace cut, and the diamond shift of it) beside the box tiles."""
+    import synth
+    u0 = synth.jacobi2d_input(NY, NX)
+    x = torch.from_numpy(u0).to("cuda:0")
+    out = torch.empty_like(x)
+    res = {}
+    best = None
+    for tile, sched in TRAP_CANDIDATES:
+        ws = pc.alloc_workspace(pc.workspace_bytes("jacobi2d", "f64", (NY, NX), T, tile, sched))
+        dt, kms = time_runs(pc, torch, x, out, ws, tile, sched, args.steps, args.warmup)
+        _, _, tr = pc.trap_plan((NY, NX), T, tile, sched)
+        bpu = 8.0 * (tr[0] + tr[1]) / UPDATES
+        key = "%s_%d_%d_%d" % ((sched,) + tuple(tile))
+        res[key] = {"gupd_s": round(UPDATES / (dt / args.steps) / 1e9, 2), "kernel_ms": round(kms, 3),
+                    "alg_bytes_per_update": round(bpu, 4)}
+        if best is None or dt < best[0]:
+            best = (dt, kms, tile, sched, bpu)
+    dt, kms, tile, sched, bpu = best
+    rec = _record("GUpdates/s, Jacobi-2D 4096^2 FP64, T=512, concurrent-start schedules (trapezoid / diamond tiles)",
+                  UPDATES / (dt / args.steps) / 1e9, "GUpdates/s", args.steps, args.warmup, dt / args.steps, "f64",
+                  "synthetic: sin(pi x)sin(pi y) + 1e-3*(2U-1) noise (SplitMix64 stream 2), zero boundary",
+                  {"workload": "jacobi2d_5pt_4096x4096_T512_f64_trap", "tile_bt_fy_fx": list(tile), "schedule": sched},
+                  _roof(UPDATES, kms / 1e3, bpu, 5), None)
+    rec["candidates"] = res
+    return rec
 
 
 def workload_heat3d(args, pc, torch, dtype):
@@ -570,7 +708,8 @@ def main():
                     help="only run the plain copy used to scale the HBM traffic counters")
     ap.add_argument("--workload", default="jacobi2d",
                     choices=["jacobi2d", "jacobi1d", "heat3d_f64", "heat3d_f32", "heat3d_bf16", "matrix_chain",
-                             "batched", "tile_variability", "paper_shapes"])
+                             "batched", "tile_variability", "paper_shapes", "gs2d", "fdtd2d", "motiv1d",
+                             "trap"])
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
@@ -592,6 +731,14 @@ def main():
             rec = workload_tile_variability(args, pc, torch)
         elif args.workload == "paper_shapes":
             rec = workload_paper_shapes(args, pc, torch)
+        elif args.workload == "gs2d":
+            rec = workload_gs2d(args, pc, torch)
+        elif args.workload == "fdtd2d":
+            rec = workload_fdtd2d(args, pc, torch)
+        elif args.workload == "motiv1d":
+            rec = workload_motiv1d(args, pc, torch)
+        elif args.workload == "trap":
+            rec = workload_trap(args, pc, torch)
         else:
             rec = workload_batched(args, pc, torch)
         print(json.dumps(rec), flush=True)

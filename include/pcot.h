@@ -47,7 +47,29 @@ extern "C" {
 typedef enum {
     PCOT_JACOBI1D_3PT = 1, /* u'[i] = ((u[i-1] + u[i]) + u[i+1]) / 3                        */
     PCOT_JACOBI2D_5PT = 2, /* u' = 0.2 * ((((c + n) + s) + e) + w), n = u[y-1][x], e = u[y][x+1] */
-    PCOT_HEAT3D_7PT = 3    /* u' = u + 0.125 * ((dx + dy) + dz), dx = (u[x+1] - 2u) + u[x-1]   */
+    PCOT_HEAT3D_7PT = 3,   /* u' = u + 0.125 * ((dx + dy) + dz), dx = (u[x+1] - 2u) + u[x-1]   */
+    PCOT_GS2D_5PT = 4,     /* in-place Gauss-Seidel: sweep t visits the interior row by row,
+                              u[y][x] = 0.2 * ((((c + n) + s) + e) + w) with n, w already of
+                              sweep t (dependences inside a time step; Section 6.2, Table 2).
+                              f64, tiled schedules 1..4 only                                  */
+    PCOT_FDTD2D = 5,       /* three-statement 2D Yee update per step, in place (an imperfect
+                              nest, run after the embedding transformation, Section 4.4):
+                                ey[i][j] -= 0.25 (hz[i][j] - hz[i-1][j])       1 <= i < ny
+                                ex[i][j] += 0.25 (hz[i][j] - hz[i][j-1])       1 <= j < nx
+                                hz[i][j] -= 0.5 ((ey[i+1][j] - ey[i][j]) - (ex[i][j+1] - ex[i][j]))
+                                                                 i < ny-1, j < nx-1
+                              in / out hold ex, ey, hz one after another (3 ny nx elements);
+                              dims are ny, nx >= 1 (no frame: every cell belongs to the nest).
+                              f64; PCOT_NAIVE (three kernels per step) or schedules 1..4  */
+    PCOT_MOTIV1D = 6       /* the appendix's motivating 1D program (Memory Allocation):
+                                x'[i] = 0.25 (((x[i-1] + x[i]) + x[i+1]) + x[0])  1 <= i <= N-2
+                                x'[0] = 0.5 x[0] + 0.25,  x'[N-1] = 0.5 x[N-1] + 0.25
+                              every interior point reads the previous step's left boundary
+                              (an affine, many-to-one dependence).  Run with the appendix's
+                              schedule-independent allocation: two buffers for the interior,
+                              single-assignment arrays of T+1 values for each boundary cell
+                              (in the workspace).  f64; PCOT_NAIVE or schedules 1..4; tile t,
+                              s[0] as for the 1D stencil                                   */
 } pcot_kind;
 
 typedef enum {
@@ -62,8 +84,16 @@ typedef enum {
     PCOT_SLT_LEX = 1,  /* single-level tiling, tiles in lexicographic order (Section 1, 3.2)   */
     PCOT_SLT_WAVE = 2, /* single-level tiling, tiles ordered by wavefront, then lexicographic  */
     PCOT_COT_SEQ = 3,  /* recursive decomposition, orthants in lexicographic order (Sec. 4.2)  */
-    PCOT_COT_PAR = 4   /* recursive decomposition, orthants grouped by wavefront at each level
+    PCOT_COT_PAR = 4,  /* recursive decomposition, orthants grouped by wavefront at each level
                           (the task/taskwait grouping of the parallel version, Sec. 4.2)      */
+    PCOT_TRAP = 5,     /* 2D stencil only: trapezoid tiles from a hyperspace cut of y and x in
+                          every time band (upright tiles shrink, inverted ones grow; the four
+                          phases UU, UV, VU, VV of a band each start all their tiles at once):
+                          the concurrent-start schedules the paper compares against (Sec. 5.3,
+                          Pochoir's Heat-3D scaling; related work, Frigo-Strumpen cuts)      */
+    PCOT_DIAMOND = 6   /* PCOT_TRAP with the cut shifted by half a period in every other band,
+                          so each upright tile sits on the inverted one below it (hexagonal /
+                          diamond tiles with concurrent start; related work, diamond tiling)  */
 } pcot_schedule;
 
 typedef int32_t pcot_status;
@@ -80,7 +110,11 @@ typedef int32_t pcot_status;
 /* Leaf (tile) sizes.  t: time steps per tile; s[0..d-1]: spatial sizes, outer
  * to inner, in skewed coordinates (j = i + t).  The same numbers are the
  * base-case thresholds of the recursive schedules.  For the interval DP,
- * s[0], s[1], s[2] are the (i, j, k) block sizes and t is unused. */
+ * s[0], s[1], s[2] are the (i, j, k) block sizes and t is unused.
+ * For PCOT_TRAP / PCOT_DIAMOND: t = band height b_t, s[0], s[1] = footprints
+ * F_y, F_x (points held per tile, one-point halo included, each >= 2 b_t + 2):
+ * upright tiles start F - 2 wide, inverted ones F - 2 b_t; executors exist
+ * for f64 with (b_t, F_y, F_x) in {(16, 64, 128), (8, 64, 128), (8, 32, 128)}. */
 typedef struct {
     int32_t t;
     int32_t s[3];
@@ -116,6 +150,21 @@ size_t pcot_stencil_workspace(int32_t kind, int32_t dtype, const int64_t* dims, 
  * larger fields return PCOT_ERR_UNSUPPORTED here and from
  * pcot_stencil_workspace (0) and the batched calls.  PCOT_NAIVE has no such
  * limit. */
+/* The tiles of a PCOT_TRAP / PCOT_DIAMOND plan of the 2D stencil, in queue
+ * order (a topological order of their dependences).  Per tile, 12 int32 in
+ * `tiles` (host, cap tiles): lo_y, hi_y, slo_y, shi_y, fo_y, lo_x, hi_x,
+ * slo_x, shi_x, fo_x, t0, nt: level l (0 <= l < nt, time step t0 + l) of the
+ * tile computes u_{t0+l+1} over [lo + slo*l, hi + shi*l) in each dimension,
+ * intersected with the interior; fo is the first index of the executor's
+ * register footprint.  `edges` (host, edge_cap pairs): (predecessor,
+ * successor) tile indices; *n_edges receives their number.  traffic[0],
+ * traffic[1] (host, nullable) receive the elements the executor loads and
+ * stores for the whole plan (its algorithmic HBM traffic).  Returns the tile
+ * count, or -1 (pcot_last_error).  Host only. */
+int64_t pcot_stencil_trap_plan(const int64_t* dims, int64_t T, const pcot_tile* tile, int32_t schedule,
+                               int32_t* tiles, int64_t cap, int32_t* edges, int64_t edge_cap,
+                               int64_t* n_edges, int64_t* traffic);
+
 pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T,
                              const pcot_tile* tile, int32_t schedule, const void* in, void* out,
                              void* workspace, size_t ws_bytes, void* stream);
@@ -199,6 +248,19 @@ size_t pcot_dp_workspace(int64_t N, const pcot_tile* tile, int32_t schedule);
 pcot_status pcot_dp_run(const int64_t* p, int64_t N, int64_t pmax, const pcot_tile* tile,
                         int32_t schedule, int64_t* C, void* workspace, size_t ws_bytes,
                         void* stream);
+
+/* Optimal parenthesization from the final cost table of pcot_dp_run: for
+ * every cell i < j (1-based A_i..A_j), split[(i-1)*N + (j-1)] = the smallest k,
+ * i <= k < j, with C[i][k] + C[k+1][j] + p[i-1] p[k] p[j] = C[i][j] (the
+ * bracketing (A_i..A_k)(A_{k+1}..A_j); a sequential scan of k with a strict
+ * comparison picks the same k).  Cells on and below the diagonal get 0.
+ *   p      device, N+1 int64 (the same dimensions as the DP run).
+ *   C      device, N*N int64 as written by pcot_dp_run (read only).
+ *   split  device, N*N int64, written.
+ * A separate pass over the finished table, so it does not depend on the
+ * order in which the tiled DP reduced its splits; it costs up to about as
+ * much work as the DP itself.  Only enqueues. */
+pcot_status pcot_dp_split(const int64_t* p, int64_t N, const int64_t* C, int64_t* split, void* stream);
 
 /* ------------------------------------------------- autotuning and model --- */
 

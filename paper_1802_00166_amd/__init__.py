@@ -26,10 +26,13 @@ _lib = ctypes.CDLL(LIB_PATH)
 # enums (include/pcot.h)
 JACOBI1D, JACOBI2D, HEAT3D = 1, 2, 3
 F64, F32, BF16 = 0, 1, 2
-NAIVE, SLT_LEX, SLT_WAVE, COT_SEQ, COT_PAR = 0, 1, 2, 3, 4
-KINDS = {"jacobi1d": JACOBI1D, "jacobi2d": JACOBI2D, "heat3d": HEAT3D}
+NAIVE, SLT_LEX, SLT_WAVE, COT_SEQ, COT_PAR, TRAP, DIAMOND = 0, 1, 2, 3, 4, 5, 6
+GS2D, FDTD2D, MOTIV1D = 4, 5, 6
+KINDS = {"jacobi1d": JACOBI1D, "jacobi2d": JACOBI2D, "heat3d": HEAT3D, "gs2d": GS2D, "fdtd2d": FDTD2D,
+         "motiv1d": MOTIV1D}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
-SCHEDULES = {"naive": NAIVE, "slt_lex": SLT_LEX, "slt_wave": SLT_WAVE, "cot_seq": COT_SEQ, "cot_par": COT_PAR}
+SCHEDULES = {"naive": NAIVE, "slt_lex": SLT_LEX, "slt_wave": SLT_WAVE, "cot_seq": COT_SEQ, "cot_par": COT_PAR,
+             "trap": TRAP, "diamond": DIAMOND}
 STATUS = {0: "OK", -1: "INVALID", -2: "UNSUPPORTED", -3: "OVERFLOW", -4: "HIP", -5: "WORKSPACE",
           -6: "TIMEOUT", -7: "DEVICE", -8: "HOST"}
 
@@ -78,11 +81,14 @@ _SIGS = {
     "pcot_stencil_run": (_I32, [_I32, _I32, _I64P, _I64, _TP, _I32, _P, _P, _P, _SZ, _P]),
     "pcot_stencil_tile_supported": (_I32, [_I32, _I32, _TP]),
     "pcot_stencil_plan": (_I64, [_I32, _I64P, _I64, _TP, _I32, ctypes.POINTER(ctypes.c_int32), _I64]),
+    "pcot_stencil_trap_plan": (_I64, [_I64P, _I64, _TP, _I32, ctypes.POINTER(ctypes.c_int32), _I64,
+                                      ctypes.POINTER(ctypes.c_int32), _I64, _I64P, _I64P]),
     "pcot_stream_status": (_I32, [_P, _P]),
     "pcot_last_error": (ctypes.c_char_p, []),
     "pcot_version": (ctypes.c_char_p, []),
     "pcot_dp_workspace": (_SZ, [_I64, _TP, _I32]),
     "pcot_dp_run": (_I32, [_P, _I64, _I64, _TP, _I32, _P, _P, _SZ, _P]),
+    "pcot_dp_split": (_I32, [_P, _I64, _P, _P, _P]),
     "pcot_stencil_workspace_batched": (_SZ, [_I32, _I32, _I32, _I64P, _I64P, _TP, _I32]),
     "pcot_stencil_run_batched": (_I32, [_I32, _I32, _I32, _I64P, _I64P, _TP, _I32, ctypes.POINTER(_P),
                                         ctypes.POINTER(_P), _P, _SZ, _P]),
@@ -181,7 +187,8 @@ def alloc_workspace(nbytes: int, device="cuda:0"):
 
 def stencil_run(kind: str, dtype: str, x, T: int, tile=None, schedule: str = "naive", out=None,
                 workspace=None, stream=None):
-    """Runs T steps on device tensor x (shape = field extents incl. boundary).
+    """Runs T steps on device tensor x (shape = field extents incl. boundary;
+    for fdtd2d a (3, ny, nx) tensor holding ex, ey, hz).
 
     bf16 fields are int16 tensors holding bfloat16 bit patterns.  Returns out.
     """
@@ -189,11 +196,14 @@ def stencil_run(kind: str, dtype: str, x, T: int, tile=None, schedule: str = "na
     assert x.is_cuda and x.is_contiguous()
     if out is None:
         out = torch.empty_like(x)
+    shape = tuple(x.shape[1:]) if kind == "fdtd2d" else tuple(x.shape)
+    if kind == "fdtd2d":
+        assert x.dim() == 3 and x.shape[0] == 3
     tp = tile if isinstance(tile, pcot_tile) else (make_tile(*tile) if tile is not None else None)
-    nbytes = workspace_bytes(kind, dtype, x.shape, T, tp, schedule)
+    nbytes = workspace_bytes(kind, dtype, shape, T, tp, schedule)
     if workspace is None or workspace.numel() < nbytes:
         workspace = alloc_workspace(nbytes, x.device)
-    st = pcot_stencil_run(KINDS[kind], DTYPES[dtype], _dims(x.shape), int(T),
+    st = pcot_stencil_run(KINDS[kind], DTYPES[dtype], _dims(shape), int(T),
                           ctypes.byref(tp) if tp is not None else None, SCHEDULES[schedule],
                           ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                           ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()),
@@ -316,6 +326,20 @@ def dp_run(p, pmax: int, tile=(0, 64, 64, 256), schedule: str = "slt_wave", out=
     return out
 
 
+def dp_split(p, C, out=None, stream=None):
+    """Optimal split (1-based k of A_k | A_{k+1}, smallest on ties) of every
+    cell from the final cost table C of dp_run; N x N int64 device tensor."""
+    torch = _torch()
+    assert p.is_cuda and C.is_cuda and p.dtype == torch.int64 and C.dtype == torch.int64
+    N = p.numel() - 1
+    assert C.shape == (N, N) and C.is_contiguous()
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.int64, device=p.device)
+    check(pcot_dp_split(ctypes.c_void_p(p.data_ptr()), int(N), ctypes.c_void_p(C.data_ptr()),
+                        ctypes.c_void_p(out.data_ptr()), stream_ptr(stream)))
+    return out
+
+
 def plan(kind: str, shape, T: int, tile, schedule: str):
     """Leaf visiting order the planner emits (host only): list of tuples."""
     tp = tile if isinstance(tile, pcot_tile) else make_tile(*tile)
@@ -326,3 +350,26 @@ def plan(kind: str, shape, T: int, tile, schedule: str):
     buf = (ctypes.c_int32 * (4 * max(n, 1)))()
     pcot_stencil_plan(KINDS[kind], _dims(shape), int(T), ctypes.byref(tp), SCHEDULES[schedule], buf, n)
     return [tuple(buf[4 * i: 4 * i + d + 1]) for i in range(n)]
+
+
+def trap_plan(shape, T: int, tile, schedule: str = "trap"):
+    """Tiles of a trapezoid plan of the 2D stencil (host only).
+
+    Returns (tiles, edges, traffic): tiles an int32 array (n, 12) of
+    lo_y, hi_y, slo_y, shi_y, fo_y, lo_x, hi_x, slo_x, shi_x, fo_x, t0, nt in
+    queue order; edges an int32 array (m, 2) of (predecessor, successor);
+    traffic (elements loaded, elements stored) by the executor."""
+    import numpy as np
+    tp = tile if isinstance(tile, pcot_tile) else make_tile(*tile)
+    ne = ctypes.c_int64(0)
+    tr = (ctypes.c_int64 * 2)()
+    n = pcot_stencil_trap_plan(_dims(shape), int(T), ctypes.byref(tp), SCHEDULES[schedule], None, 0, None, 0,
+                               ctypes.byref(ne), tr)
+    if n < 0:
+        raise PcotError(-1, last_error())
+    tiles = np.zeros((max(n, 1), 12), dtype=np.int32)
+    edges = np.zeros((max(ne.value, 1), 2), dtype=np.int32)
+    pcot_stencil_trap_plan(_dims(shape), int(T), ctypes.byref(tp), SCHEDULES[schedule],
+                           tiles.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n,
+                           edges.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ne.value, ctypes.byref(ne), tr)
+    return tiles[:n], edges[:ne.value], (int(tr[0]), int(tr[1]))

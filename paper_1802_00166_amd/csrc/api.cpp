@@ -16,6 +16,10 @@
 #include "../../include/pcot.h"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "trap.hpp"
+#include "front.hpp"
+#include "motiv.hpp"
+#include "dpsplit.hpp"
 
 namespace pcot {
 enum : int { DP_INIT = 0, DP_ITEMS = 1, DP_FINISH = 2 };
@@ -67,9 +71,23 @@ constexpr size_t ALIGN = 256;
 constexpr uint32_t TILED_MAX_OFFSET = 0x7FFFFFF0u;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
+bool is_trap(int schedule) { return schedule == PCOT_TRAP || schedule == PCOT_DIAMOND; }
+
 size_t elem_bytes(int dtype) { return dtype == PCOT_F64 ? 8 : dtype == PCOT_F32 ? 4 : 2; }
 
-int kind_dims(int kind) { return kind == PCOT_JACOBI1D_3PT ? 1 : kind == PCOT_JACOBI2D_5PT ? 2 : kind == PCOT_HEAT3D_7PT ? 3 : 0; }
+int kind_dims(int kind) {
+    switch (kind) {
+        case PCOT_JACOBI1D_3PT: case PCOT_MOTIV1D: return 1;
+        case PCOT_JACOBI2D_5PT: case PCOT_GS2D_5PT: case PCOT_FDTD2D: return 2;
+        case PCOT_HEAT3D_7PT: return 3;
+        default: return 0;
+    }
+}
+
+// Kinds updated in place by the front executor (dependences inside a step).
+bool is_front(int kind) { return kind == PCOT_GS2D_5PT || kind == PCOT_FDTD2D; }
+// Fields of a kind (FDTD-2D: ex, ey, hz one after another).
+int kind_fields(int kind) { return kind == PCOT_FDTD2D ? 3 : 1; }
 
 long long watchdog_ticks() {
     // wall_clock64 runs at hipDeviceAttributeWallClockRate kHz; allow 4 s.
@@ -101,13 +119,21 @@ pcot_status validate(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T
     p.sched = schedule;
     if (!p.d) return fail(PCOT_ERR_INVALID, "unknown kind %d", kind);
     if (dtype < PCOT_F64 || dtype > PCOT_BF16) return fail(PCOT_ERR_INVALID, "unknown dtype %d", dtype);
-    if (schedule < PCOT_NAIVE || schedule > PCOT_COT_PAR) return fail(PCOT_ERR_INVALID, "unknown schedule %d", schedule);
+    if (schedule < PCOT_NAIVE || schedule > PCOT_DIAMOND) return fail(PCOT_ERR_INVALID, "unknown schedule %d", schedule);
+    if (is_trap(schedule) && kind != PCOT_JACOBI2D_5PT)
+        return fail(PCOT_ERR_UNSUPPORTED, "trapezoid schedules are built for the Jacobi-2D stencil only");
+    if ((is_front(kind) || kind == PCOT_MOTIV1D) && dtype != PCOT_F64)
+        return fail(PCOT_ERR_UNSUPPORTED, "Gauss-Seidel-2D, FDTD-2D and the motivating 1D program run in f64 only");
+    if (kind == PCOT_GS2D_5PT && schedule == PCOT_NAIVE)
+        return fail(PCOT_ERR_UNSUPPORTED, "Gauss-Seidel-2D has no untiled executor (its sweep is sequential)");
     if (!dims) return fail(PCOT_ERR_INVALID, "dims is NULL");
     if (T < 0 || T > (1 << 30)) return fail(PCOT_ERR_INVALID, "T=%lld out of range", (long long)T);
     p.T = T;
     p.elems = 1;
     for (int i = 0; i < p.d; ++i) {
-        if (dims[i] < 3 || dims[i] > (1LL << 30)) return fail(PCOT_ERR_INVALID, "dims[%d]=%lld (need 3 .. 2^30)", i, (long long)dims[i]);
+        const int64_t lo = kind == PCOT_FDTD2D ? 1 : 3;  // FDTD cells have no fixed frame
+        if (dims[i] < lo || dims[i] > (1LL << 30))
+            return fail(PCOT_ERR_INVALID, "dims[%d]=%lld (need %lld .. 2^30)", i, (long long)dims[i], (long long)lo);
         p.n[i] = dims[i];
         p.elems *= dims[i];
     }
@@ -120,6 +146,11 @@ pcot_status validate(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T
             if (tile->s[i] < 2) return fail(PCOT_ERR_INVALID, "tile.s[%d]=%d < 2 (dependence distance is 2)", i, tile->s[i]);
             p.b[i + 1] = tile->s[i];
         }
+        if (is_trap(schedule))
+            for (int i = 0; i < 2; ++i)
+                if (tile->s[i] < 2 * tile->t + 2)
+                    return fail(PCOT_ERR_INVALID, "trapezoid footprint s[%d]=%d < 2*t+2 = %d", i, tile->s[i],
+                                2 * tile->t + 2);
         // The tiled executors address a field through one buffer resource
         // with 32-bit byte offsets and mask stores with the offset OOB
         // (0x7FFFFFF0).  Offsets they form reach one outermost slice (row,
@@ -135,12 +166,15 @@ pcot_status validate(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T
     return PCOT_OK;
 }
 
-bool tile_ok(int kind, int dtype, const int* b) {
+bool tile_ok(int kind, int dtype, const int* b, int schedule = PCOT_SLT_WAVE) {
+    if (is_trap(schedule)) return kind == PCOT_JACOBI2D_5PT && trap2d_supported(dtype, b[0], b[1], b[2]);
+    if (is_front(kind)) return front2d_supported(kind, dtype, b);
+    if (kind == PCOT_MOTIV1D) return dtype == PCOT_F64 && motiv_supported(b);
     int bb[4] = {b[0], b[1], b[2], b[3]};
     switch (kind) {
         case PCOT_JACOBI1D_3PT: return tiled1d_supported(bb);
         case PCOT_JACOBI2D_5PT: return tiled2d_supported(bb);
-        default: return tiled3d_supported(bb, dtype == PCOT_F64 ? 8 : 4);
+        default: return tiled3d_supported(bb, dtype == PCOT_F64 ? 8 : dtype == PCOT_F32 ? 4 : 2);
     }
 }
 
@@ -160,13 +194,20 @@ std::map<std::vector<int64_t>, std::unique_ptr<DevPlan>> g_plans;
 
 StencilGeom geom_of(const Prob& p) {
     int64_t tb[4] = {p.b[0], p.b[1], p.b[2], p.b[3]};
+    if (p.kind == PCOT_FDTD2D) {
+        // the embedded FDTD nest runs over all ny x nx cells: planned as a
+        // stencil whose interior is that grid
+        const int64_t n2[3] = {p.n[0] + 2, p.n[1] + 2, 1};
+        return make_geom(p.d, n2, p.T, tb);
+    }
     return make_geom(p.d, p.n, p.T, tb);
 }
 
 pcot_status get_plan(const Prob& p, DevPlan** out) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    std::vector<int64_t> key = {dev, p.d, p.n[0], p.n[1], p.n[2], p.T, p.b[0], p.b[1], p.b[2], p.b[3], p.sched};
+    std::vector<int64_t> key = {dev, p.d, p.n[0], p.n[1], p.n[2], p.T, p.b[0], p.b[1], p.b[2], p.b[3], p.sched,
+                                p.kind == PCOT_FDTD2D};
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
@@ -192,9 +233,65 @@ pcot_status get_plan(const Prob& p, DevPlan** out) {
     return PCOT_OK;
 }
 
+// Trapezoid plans: built once per geometry on the host, uploaded per device.
+struct TrapPlan {
+    TrapPlanHost host;
+    std::map<int, std::pair<TrapTile*, int*>> dev;
+    ~TrapPlan() {
+        for (auto& kv : dev) {
+            if (kv.second.first) (void)hipFree(kv.second.first);
+            if (kv.second.second) (void)hipFree(kv.second.second);
+        }
+    }
+};
+std::map<std::vector<int64_t>, std::unique_ptr<TrapPlan>> g_trap_plans;
+
+TrapPlan* trap_plan_host(const Prob& p) {  // caller holds g_mu
+    std::vector<int64_t> key = {p.n[0], p.n[1], p.T, p.b[0], p.b[1], p.b[2], p.sched};
+    auto it = g_trap_plans.find(key);
+    if (it != g_trap_plans.end()) return it->second.get();
+    auto P = std::make_unique<TrapPlan>();
+    const int F[2] = {p.b[1], p.b[2]};
+    P->host = build_trap_plan((int)p.n[0], (int)p.n[1], (int)p.T, p.b[0], F, p.sched == PCOT_DIAMOND);
+    TrapPlan* r = P.get();
+    g_trap_plans.emplace(key, std::move(P));
+    return r;
+}
+
+size_t trap_tile_count(const Prob& p) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return trap_plan_host(p)->host.tiles.size();
+}
+
+pcot_status get_trap_plan(const Prob& p, TrapPlan** out, TrapTile** dt, int** ds) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    TrapPlan* P = trap_plan_host(p);
+    auto it = P->dev.find(dev);
+    if (it == P->dev.end()) {
+        TrapTile* t = nullptr;
+        int* s = nullptr;
+        const size_t nt = P->host.tiles.size(), ns = P->host.succ.size();
+        if (nt) {
+            HIP_TRY(hipMalloc(&t, sizeof(TrapTile) * nt));
+            HIP_TRY(hipMemcpy(t, P->host.tiles.data(), sizeof(TrapTile) * nt, hipMemcpyHostToDevice));
+        }
+        if (ns) {
+            HIP_TRY(hipMalloc(&s, sizeof(int) * ns));
+            HIP_TRY(hipMemcpy(s, P->host.succ.data(), sizeof(int) * ns, hipMemcpyHostToDevice));
+        }
+        it = P->dev.emplace(dev, std::make_pair(t, s)).first;
+    }
+    *out = P;
+    *dt = it->second.first;
+    *ds = it->second.second;
+    return PCOT_OK;
+}
+
 // ------------------------------------------------------------ workspace ---
 struct WsLayout {
-    size_t hdr = 0, probs = 0, counters = 0, field = 0, total = 0;
+    size_t hdr = 0, probs = 0, counters = 0, field = 0, aux = 0, total = 0;
     size_t ncounters = 0;
 };
 
@@ -204,7 +301,12 @@ WsLayout ws_layout(const Prob& p) {
     size_t off = align_up(HDR_WORDS * sizeof(unsigned));
     L.probs = off;
     off += align_up(sizeof(TiledProblem));
-    if (p.sched != PCOT_NAIVE) {
+    if (is_trap(p.sched)) {
+        const size_t nc = std::max<size_t>(1, trap_tile_count(p));
+        L.ncounters = nc;
+        L.counters = off;
+        off += align_up(nc * sizeof(unsigned));
+    } else if (p.sched != PCOT_NAIVE) {
         StencilGeom g = geom_of(p);
         size_t nc = 1;
         for (int i = 0; i <= p.d; ++i) nc *= (size_t)g.cnt[i];
@@ -213,7 +315,11 @@ WsLayout ws_layout(const Prob& p) {
         off += align_up(nc * sizeof(unsigned));
     }
     L.field = off;
-    off += align_up((size_t)p.elems * elem_bytes(p.dtype));
+    if (!is_front(p.kind)) off += align_up((size_t)p.elems * elem_bytes(p.dtype));  // in-place kinds need none
+    if (p.kind == PCOT_MOTIV1D) {  // Y[0..T], Z[0..T]
+        L.aux = off;
+        off += align_up(2 * (size_t)(p.T + 1) * sizeof(double));
+    }
     L.total = off;
     return L;
 }
@@ -476,6 +582,9 @@ pcot_status batch_validate(int32_t kind, int32_t dtype, int32_t n, const int64_t
     if (n < 1 || n > 65535) return fail(PCOT_ERR_INVALID, "batch of %d instances (need 1 .. 65535)", n);
     if (!dims || !T || !tiles) return fail(PCOT_ERR_INVALID, "dims/T/tiles is NULL");
     if (schedule == PCOT_NAIVE) return fail(PCOT_ERR_UNSUPPORTED, "batched runs need a tiled schedule");
+    if (is_trap(schedule)) return fail(PCOT_ERR_UNSUPPORTED, "batched runs take the box-tile schedules (1..4)");
+    if (is_front(kind) || kind == PCOT_MOTIV1D)
+        return fail(PCOT_ERR_UNSUPPORTED, "batched runs take the Jacobi and Heat-3D kinds");
     B.p.resize(n);
     for (int i = 0; i < n; ++i) {
         pcot_status st = validate(kind, dtype, dims + 3 * (size_t)i, T[i], tiles + i, schedule, B.p[i]);
@@ -637,6 +746,7 @@ int64_t pcot_stencil_plan(int32_t kind, const int64_t* dims, int64_t T, const pc
     PCOT_TRY
     Prob p;
     if (schedule == PCOT_NAIVE) { fail(PCOT_ERR_INVALID, "naive schedule has no plan"); return -1; }
+    if (is_trap(schedule)) { fail(PCOT_ERR_INVALID, "trapezoid plans: pcot_stencil_trap_plan"); return -1; }
     if (validate(kind, PCOT_F64, dims, T, tile, schedule, p) != PCOT_OK) return -1;
     StencilGeom g = geom_of(p);
     std::vector<Leaf> leaves = enumerate_leaves(g, schedule);
@@ -644,6 +754,39 @@ int64_t pcot_stencil_plan(int32_t kind, const int64_t* dims, int64_t T, const pc
         for (int64_t i = 0; i < (int64_t)leaves.size() && i < cap; ++i)
             for (int j = 0; j < 4; ++j) order[4 * i + j] = leaves[i].k[j];
     return (int64_t)leaves.size();
+    PCOT_CATCH(-1)
+}
+
+int64_t pcot_stencil_trap_plan(const int64_t* dims, int64_t T, const pcot_tile* tile, int32_t schedule,
+                               int32_t* tiles, int64_t cap, int32_t* edges, int64_t edge_cap, int64_t* n_edges,
+                               int64_t* traffic) {
+    PCOT_TRY
+    Prob p;
+    if (!is_trap(schedule)) { fail(PCOT_ERR_INVALID, "schedule %d is not a trapezoid schedule", schedule); return -1; }
+    if (validate(PCOT_JACOBI2D_5PT, PCOT_F64, dims, T, tile, schedule, p) != PCOT_OK) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const TrapPlanHost& H = trap_plan_host(p)->host;
+    const int64_t nt = (int64_t)H.tiles.size();
+    if (tiles)
+        for (int64_t i = 0; i < nt && i < cap; ++i) {
+            const TrapTile& t = H.tiles[i];
+            const int32_t rec[12] = {t.lo[0], t.hi[0], t.slo[0], t.shi[0], t.fo[0], t.lo[1],
+                                     t.hi[1], t.slo[1], t.shi[1], t.fo[1], t.t0, t.nt};
+            memcpy(tiles + 12 * i, rec, sizeof rec);
+        }
+    int64_t ne = 0;
+    for (int64_t i = 0; i < nt; ++i)
+        for (int k = 0; k < H.tiles[i].nsucc; ++k, ++ne)
+            if (edges && ne < edge_cap) {
+                edges[2 * ne] = (int32_t)i;
+                edges[2 * ne + 1] = H.succ[H.tiles[i].succ0 + k];
+            }
+    if (n_edges) *n_edges = ne;
+    if (traffic) {
+        traffic[0] = H.loads;
+        traffic[1] = H.stores;
+    }
+    return nt;
     PCOT_CATCH(-1)
 }
 
@@ -656,13 +799,13 @@ pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, i
     if (st != PCOT_OK) return st;
     if (!in || !out) return fail(PCOT_ERR_INVALID, "in/out is NULL");
     hipStream_t s = (hipStream_t)stream;
-    const size_t bytes = (size_t)p.elems * elem_bytes(dtype);
+    const size_t bytes = (size_t)p.elems * elem_bytes(dtype) * kind_fields(kind);
     {
         const char* a = (const char*)in;
         const char* b = (const char*)out;
         if (a < b + bytes && b < a + bytes) return fail(PCOT_ERR_INVALID, "in and out overlap");
     }
-    if (schedule != PCOT_NAIVE && !tile_ok(kind, dtype, p.b))
+    if (schedule != PCOT_NAIVE && !tile_ok(kind, dtype, p.b, schedule))
         return fail(PCOT_ERR_UNSUPPORTED, "tile (%d; %d,%d,%d) not runnable for kind %d dtype %d", p.b[0], p.b[1],
                     p.b[2], p.b[3], kind, dtype);
     if (T == 0) {
@@ -683,6 +826,83 @@ pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, i
         const char* c = (const char*)in;
         if (a < c + bytes && c < a + W.total) return fail(PCOT_ERR_INVALID, "in overlaps the workspace");
     }
+    if (is_front(kind)) {
+        // in place on out: every field copied first
+        HIP_TRY(hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s));
+        const size_t fe = (size_t)p.elems;
+        double* f0 = (double*)out;
+        if (schedule == PCOT_NAIVE) {  // FDTD-2D only (validated)
+            for (int64_t t = 0; t < T; ++t)
+                HIP_TRY(launch_fdtd2d_step(f0, f0 + fe, f0 + 2 * fe, (int)p.n[0], (int)p.n[1], s));
+            return PCOT_OK;
+        }
+        DevPlan* plan = nullptr;
+        st = get_plan(p, &plan);
+        if (st != PCOT_OK) return st;
+        unsigned* counters = (unsigned*)(ws + W.counters);
+        HIP_TRY(launch_fill_u32(hdr, HDR_WORDS, 0u, s));
+        HIP_TRY(launch_fill_u32(counters, W.ncounters, 0u, s));
+        if (plan->host.empty()) return PCOT_OK;
+        TiledProblem P = make_tiled(p, plan, f0, f0, f0, counters);
+        if (kind == PCOT_FDTD2D) {
+            // ex, ey, hz; the planner's extents include the embedding's frame
+            P.buf0 = f0;
+            P.buf1 = f0 + fe;
+            P.in = f0 + 2 * fe;
+            P.n[0] = (int)p.n[0] + 2;
+            P.n[1] = (int)p.n[1] + 2;
+        }
+        TiledProblem* probs = (TiledProblem*)(ws + W.probs);
+        HIP_TRY(launch_put_problem(probs, P, s));
+        TiledLaunch L;
+        memset(&L, 0, sizeof L);
+        L.probs = probs;
+        L.queue = plan->dev;
+        L.nq = (int)plan->host.size();
+        L.hdr = hdr;
+        L.limit_ticks = watchdog_ticks();
+        hipEvent_t stop;
+        st = timed_launch_begin(s, &stop);
+        if (st != PCOT_OK) return st;
+        HIP_TRY(launch_front2d(kind, p.b, L, s));
+        return timed_launch_end(s, stop);
+    }
+    if (kind == PCOT_MOTIV1D) {
+        double* Y = (double*)(ws + W.aux);
+        double* Z = Y + (T + 1);
+        const int N = (int)p.n[0];
+        HIP_TRY(launch_motiv_boundary((const double*)in, Y, Z, (double*)out, N, (int)T, s));
+        void* buf[2];
+        buf[T & 1] = out;
+        buf[(T + 1) & 1] = field;
+        if (schedule == PCOT_NAIVE) {
+            for (int64_t t = 0; t < T; ++t)
+                HIP_TRY(launch_motiv_step((const double*)(t == 0 ? in : buf[t & 1]), (double*)buf[(t + 1) & 1], Y,
+                                          Z, N, (int)t, s));
+            return PCOT_OK;
+        }
+        DevPlan* plan = nullptr;
+        st = get_plan(p, &plan);
+        if (st != PCOT_OK) return st;
+        unsigned* counters = (unsigned*)(ws + W.counters);
+        HIP_TRY(launch_fill_u32(hdr, HDR_WORDS, 0u, s));
+        HIP_TRY(launch_fill_u32(counters, W.ncounters, 0u, s));
+        if (plan->host.empty()) return PCOT_OK;
+        TiledProblem* probs = (TiledProblem*)(ws + W.probs);
+        HIP_TRY(launch_put_problem(probs, make_tiled(p, plan, in, out, field, counters), s));
+        TiledLaunch L;
+        memset(&L, 0, sizeof L);
+        L.probs = probs;
+        L.queue = plan->dev;
+        L.nq = (int)plan->host.size();
+        L.hdr = hdr;
+        L.limit_ticks = watchdog_ticks();
+        hipEvent_t stop;
+        st = timed_launch_begin(s, &stop);
+        if (st != PCOT_OK) return st;
+        HIP_TRY(launch_motiv_tiles(p.b, L, Y, Z, s));
+        return timed_launch_end(s, stop);
+    }
     // buffers: buf[T mod 2] = out, the other one in the workspace; both get in's boundary
     HIP_TRY(launch_copy_boundary(dtype, in, out, field, p.d, p.n, s));
     if (schedule == PCOT_NAIVE) {
@@ -695,6 +915,36 @@ pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, i
             HIP_TRY(launch_step(kind, dtype, src, buf[(t + 1) & 1], p.n, s));
         }
         return PCOT_OK;
+    }
+    if (is_trap(schedule)) {
+        TrapPlan* tp = nullptr;
+        TrapTile* dt = nullptr;
+        int* ds = nullptr;
+        st = get_trap_plan(p, &tp, &dt, &ds);
+        if (st != PCOT_OK) return st;
+        unsigned* counters = (unsigned*)(ws + W.counters);
+        HIP_TRY(launch_fill_u32(hdr, HDR_WORDS, 0u, s));
+        HIP_TRY(launch_fill_u32(counters, W.ncounters, 0u, s));
+        if (tp->host.tiles.empty()) return PCOT_OK;
+        TrapLaunch L;
+        memset(&L, 0, sizeof L);
+        L.tiles = dt;
+        L.succ = ds;
+        L.counters = counters;
+        L.hdr = hdr;
+        L.in = in;
+        // u_T lands in buf[T mod 2] = out
+        L.buf0 = (T & 1) ? field : out;
+        L.buf1 = (T & 1) ? out : field;
+        L.ntiles = (int)tp->host.tiles.size();
+        L.ny = (int)p.n[0];
+        L.nx = (int)p.n[1];
+        L.limit_ticks = watchdog_ticks();
+        hipEvent_t stop;
+        st = timed_launch_begin(s, &stop);
+        if (st != PCOT_OK) return st;
+        HIP_TRY(launch_trap2d(dtype, p.b[0], p.b[1], p.b[2], L, s));
+        return timed_launch_end(s, stop);
     }
     DevPlan* plan = nullptr;
     st = get_plan(p, &plan);
@@ -898,6 +1148,16 @@ pcot_status pcot_dp_run(const int64_t* p, int64_t N, int64_t pmax, const pcot_ti
         HIP_TRY(launch_dp_phase(A.wide, L, DP_FINISH, s));
     }
     return timed_launch_end(s, stop);
+    PCOT_CATCH(PCOT_ERR_HOST)
+}
+
+pcot_status pcot_dp_split(const int64_t* p, int64_t N, const int64_t* C, int64_t* split, void* stream) {
+    PCOT_TRY
+    if (N < 1 || N > 65535) return fail(PCOT_ERR_INVALID, "N=%lld (need 1 .. 65535)", (long long)N);
+    if (!p || !C || !split) return fail(PCOT_ERR_INVALID, "p/C/split is NULL");
+    HIP_TRY(launch_dp_split((const long long*)p, (const long long*)C, (long long*)split, (int)N,
+                            (hipStream_t)stream));
+    return PCOT_OK;
     PCOT_CATCH(PCOT_ERR_HOST)
 }
 

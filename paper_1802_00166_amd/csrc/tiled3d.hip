@@ -27,9 +27,27 @@ namespace pcot {
 
 namespace {
 
+// Ring storage: the arithmetic type, except for bf16 storage, whose rings
+// hold the 16-bit patterns.  Every value a bf16 ring receives is already a
+// bf16 number (inputs read from bf16 storage, outputs rounded to bf16 by the
+// update), so keeping its upper 16 bits is exact and halves the LDS a level
+// needs.
+template <typename S> struct Ring {
+    using L = typename Tr<S>::A;
+    static __device__ __forceinline__ L put(typename Tr<S>::A v) { return v; }
+    static __device__ __forceinline__ typename Tr<S>::A get(L v) { return v; }
+};
+template <> struct Ring<uint16_t> {
+    using L = uint16_t;
+    static __device__ __forceinline__ L put(float v) { return (uint16_t)(__float_as_uint(v) >> 16); }
+    static __device__ __forceinline__ float get(L v) { return bf16_to_f32(v); }
+};
+
 template <typename S, int BY, bool BND>
-__device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, typename Tr<S>::A* lds) {
+__device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, typename Ring<S>::L* lds) {
     using A = typename Tr<S>::A;
+    using L = typename Ring<S>::L;
+    using RG = Ring<S>;
     constexpr int ES = sizeof(S);
     constexpr int BX = 64, RX = BX + 2;
     const int lane = threadIdx.x & 63;
@@ -58,7 +76,7 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     // is published at step s), so at step s every level reads slots s-1, s-2,
     // s-3 and writes slot s: with the step loop unrolled by four, all ring
     // addresses of a level are one base plus constants.
-    auto ring = [&](int v, int jz, int ry, int rx) -> A& {
+    auto ring = [&](int v, int jz, int ry, int rx) -> L& {
         return lds[((v * 4 + ((jz - jz0 + v + 3) & 3)) * RY + ry) * RX + rx];
     };
     // ring v's value at skewed (jz, jy, jx): u_{t0+v} at the point
@@ -78,7 +96,7 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
             const int pz = e / PL, rem = e % PL;
             const int ry = rem / RX, rx = rem % RX;
             const int jz = jz0 - 2 + pz;
-            ring(v, jz, ry, rx) = ldlvl(v, jz, jy0 - 2 + ry, jx0 - 2 + rx);
+            ring(v, jz, ry, rx) = RG::put(ldlvl(v, jz, jy0 - 2 + ry, jx0 - 2 + rx));
         }
     }
     // Prefetch slots: every thread owns fixed positions of the ring-0 plane
@@ -112,10 +130,10 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
                 p0[i] = IO<S>::ld(r0, (zok && p_yok[i]) ? (int)(p_off[i] + (uint32_t)s * PB) : OOB);
     };
     auto pf0_store = [&](int jz) {
-        A* pl = &ring(0, jz, 0, 0);
+        L* pl = &ring(0, jz, 0, 0);
 #pragma unroll
         for (int i = 0; i < PF; ++i)
-            if (p_lds[i] >= 0) pl[p_lds[i]] = p0[i];
+            if (p_lds[i] >= 0) pl[p_lds[i]] = RG::put(p0[i]);
     };
     // halo of plane jz of ring v (v >= 1): rows ry = 0, 1 (all RX columns) and
     // columns rx = 0, 1 of rows 2..RY-1: 2*RX + 2*by values per level
@@ -163,7 +181,7 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
 #pragma unroll
         for (int i = 0; i < HPF; ++i) {
             const int l = h_l[i], sl = s - l;
-            if (l < nt && (uint32_t)sl < (uint32_t)bz) (&ring(l + 1, jz0 + sl, 0, 0))[h_lds[i]] = hv[i];
+            if (l < nt && (uint32_t)sl < (uint32_t)bz) (&ring(l + 1, jz0 + sl, 0, 0))[h_lds[i]] = RG::put(hv[i]);
         }
     };
     pf0_load(-1);  // plane jz0 + 1
@@ -189,14 +207,15 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
             const int jz = jz0 + s - l;
             if (jz < jz0 || jz >= jz0 + bz) continue;  // uniform
             const int t = t0 + l;
-            const A* rl = lds + l * (4 * PL) + tc;  // ring l around the centre input
-            const A u = rl[SC * PL];
-            const A v = Tr<S>::rnd(heat3(u, rl[SC * PL + 1], rl[SC * PL - 1], rl[SC * PL + RX], rl[SC * PL - RX],
-                                         rl[SP * PL], rl[SM * PL]));
+            const L* rl = lds + l * (4 * PL) + tc;  // ring l around the centre input
+            const A u = RG::get(rl[SC * PL]);
+            const A v = Tr<S>::rnd(heat3(u, RG::get(rl[SC * PL + 1]), RG::get(rl[SC * PL - 1]),
+                                         RG::get(rl[SC * PL + RX]), RG::get(rl[SC * PL - RX]),
+                                         RG::get(rl[SP * PL]), RG::get(rl[SM * PL])));
             const int z = jz - t, y = jy - t, x = jx - t;
             const bool in = !BND || inside(z, y, x);
             const A out = in ? v : u;
-            lds[(l + 1) * (4 * PL) + SW * PL + ry * RX + rx] = out;
+            lds[(l + 1) * (4 * PL) + SW * PL + ry * RX + rx] = RG::put(out);
             const bool face = t == ttop || lane >= BX - 2 || w >= by - 2 || jz >= jz0 + bz - 2;
             // level l writes u_{t0+l+1}: the buffers of rings l+1 (hoisted descriptors)
             if (face && in) IO<S>::st((l & 1) ? rhO : rhE, offs(z, y, x), out);
@@ -214,14 +233,14 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
 template <typename S, int BY>
 __global__ void __launch_bounds__(64 * BY) k_tiled3d(TiledLaunch Lc) {
     extern __shared__ char smem_raw[];
-    using A = typename Tr<S>::A;
+    using L = typename Ring<S>::L;
     __shared__ int s_tk, s_go;
     run_queued_tile<3, true>(Lc, &s_tk, &s_go, [&](const TiledProblem& P, const int* k) {
         // tiles whose every point lies inside the array skip the per-point test
         if (tile_interior<3>(P, k))
-            exec3d<S, BY, false>(P, k, reinterpret_cast<A*>(smem_raw));
+            exec3d<S, BY, false>(P, k, reinterpret_cast<L*>(smem_raw));
         else
-            exec3d<S, BY, true>(P, k, reinterpret_cast<A*>(smem_raw));
+            exec3d<S, BY, true>(P, k, reinterpret_cast<L*>(smem_raw));
     });
 }
 
@@ -238,9 +257,8 @@ hipError_t launch_by(const TiledLaunch& Lc, size_t lds, hipStream_t s) {
 template <typename S>
 hipError_t launch_dtype(const int* b, const TiledLaunch& Lc, hipStream_t s) {
     if (Lc.nq <= 0) return hipSuccess;
-    using A = typename Tr<S>::A;
     const int bt = b[0], by = b[2];
-    const size_t lds = (size_t)(bt + 1) * 4 * (by + 2) * 66 * sizeof(A);
+    const size_t lds = (size_t)(bt + 1) * 4 * (by + 2) * 66 * sizeof(typename Ring<S>::L);
     switch (by) {
         case 2: return launch_by<S, 2>(Lc, lds, s);
         case 4: return launch_by<S, 4>(Lc, lds, s);
@@ -253,7 +271,7 @@ hipError_t launch_dtype(const int* b, const TiledLaunch& Lc, hipStream_t s) {
 }  // namespace
 
 bool tiled3d_supported(const int* b, int lds_elem) {
-    // b = {bt, bz, by, bx}; lds_elem: bytes of one ring value (8 for f64, 4 otherwise)
+    // b = {bt, bz, by, bx}; lds_elem: bytes of one ring value (8 f64, 4 f32, 2 bf16)
     if (b[3] != 64) return false;
     if (b[2] != 2 && b[2] != 4 && b[2] != 8 && b[2] != 16) return false;
     if (b[1] < 2 || b[0] < 1 || b[0] > 16) return false;

@@ -91,3 +91,52 @@ def test_chain_full_size(gpu):
     for tile, sched in [(bench.CHAIN_TILE, "slt_wave"), ((0, 64, 64, 256), "slt_wave"),
                         ((0, 64, 64, 256), "cot_par")]:
         assert np.array_equal(_upper(_run(p, 100, tile, sched)), want), sched
+
+
+def _split(p_np, pmax, tile, sched):
+    import torch
+    import paper_1802_00166_amd as pc
+    p = torch.from_numpy(np.ascontiguousarray(p_np, dtype=np.int64)).to("cuda:0")
+    C = pc.dp_run(p, pmax, tile, sched)
+    S = pc.dp_split(p, C)
+    torch.cuda.synchronize()
+    return C.cpu().numpy(), S.cpu().numpy()
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 7, 64, 300, 1000])
+def test_chain_split_matches_oracle(gpu, N):
+    """The parenthesization: smallest optimal k per cell (1-based, the
+    oracle's sequential strict-minimum scan), zero on and below the diagonal."""
+    p = synth.randint(synth.test_rng(90 + N), N + 1, 1, 100)
+    C, S = _split(p, 100, (0, 32, 32, 32), "slt_wave")
+    wC, wS = oracle.matrix_chain(p, want_split=True)
+    assert np.array_equal(_upper(C), _upper(wC))
+    assert np.array_equal(S, wS)
+
+
+def test_chain_split_uniform_ties_take_smallest_k(gpu):
+    """Uniform p: every split of a cell ties, so the split is the cell's
+    first index (k = i)."""
+    N = 200
+    p = np.full(N + 1, 7, dtype=np.int64)
+    C, S = _split(p, 7, (0, 32, 32, 32), "cot_par")
+    i, j = np.triu_indices(N, 1)
+    assert np.array_equal(S[i, j], i + 1)
+    assert not S[np.tril_indices(N)].any()
+
+
+def test_chain_split_reconstructs_cost(gpu):
+    """Rebuilding the bracketing from split and summing its products gives
+    C[1][N] (a property of any valid split table)."""
+    N = 500
+    p = synth.randint(synth.test_rng(95), N + 1, 1, 100)
+    C, S = _split(p, 100, (0, 64, 64, 32), "slt_wave")
+
+    def cost(i, j):   # 0-based cell (i, j)
+        if i == j:
+            return 0
+        k = int(S[i, j])   # 1-based: A_k | A_{k+1}  ->  0-based split k - 1
+        return cost(i, k - 1) + cost(k, j) + int(p[i]) * int(p[k]) * int(p[j + 1])
+    import sys
+    sys.setrecursionlimit(10000)
+    assert cost(0, N - 1) == int(C[0, N - 1])

@@ -147,3 +147,58 @@ def test_planner_matches_hand_enumerated_2d_orders():
     for sched in ("slt_lex", "slt_wave", "cot_seq", "cot_par"):
         got = pc.plan("jacobi2d", tuple(pr["dims"]), pr["T"], tuple(pr["tile"]), sched)
         assert [list(k) for k in got] == g[sched], sched
+
+
+# ------------------------------------------------ trapezoid plans (host) ---
+@pytest.mark.parametrize("sched", ["trap", "diamond"])
+@pytest.mark.parametrize("shape,T,tile", [
+    ((130, 300), 40, (16, 64, 128)),
+    ((61, 77), 29, (8, 64, 128)),
+    ((300, 520), 33, (8, 32, 128)),
+    ((3, 3), 5, (8, 64, 128)),
+    ((4, 700), 17, (16, 64, 128)),
+    ((700, 5), 9, (8, 64, 128)),
+    ((200, 200), 64, (8, 20, 30)),     # planner geometry at any footprint
+])
+def test_trap_plan_legal_by_brute_force(shape, T, tile, sched):
+    import oracle
+    import paper_1802_00166_amd as pc
+    tiles, edges, traffic = pc.trap_plan(shape, T, tile, sched)
+    assert oracle.check_trap_plan(shape, T, tiles, edges, tile[1:]) == []
+    assert traffic[1] >= (shape[0] - 2) * (shape[1] - 2)   # every point stored at least at the end
+
+
+def test_trap_plan_checker_catches_planted_mistakes():
+    """The brute-force checker flags a dropped dependence, a range off by one
+    and a tile out of queue order (mistakes planted in the plan it is given)."""
+    import oracle
+    import paper_1802_00166_amd as pc
+    shape, T, tile = (130, 300), 40, (16, 64, 128)
+    tiles, edges, _ = pc.trap_plan(shape, T, tile, "trap")
+    assert oracle.check_trap_plan(shape, T, tiles, edges, tile[1:]) == []
+    probs = oracle.check_trap_plan(shape, T, tiles, edges[1:], tile[1:])
+    assert any(p[0] == "dependence" for p in probs)
+    bad = tiles.copy()
+    bad[0, 1] += 1                      # upright tile one row taller: overlaps its neighbour
+    assert oracle.check_trap_plan(shape, T, bad, edges, tile[1:])
+    rev = edges.copy()
+    rev[0] = rev[0][::-1]
+    assert any(p[0] == "edge order" for p in oracle.check_trap_plan(shape, T, tiles, rev, tile[1:]))
+
+
+def test_trap_plan_refused_for_other_kinds_and_small_footprints():
+    import paper_1802_00166_amd as pc
+    with pytest.raises(pc.PcotError):
+        pc.trap_plan((100, 100), 10, (16, 30, 128), "trap")    # F_y < 2 b_t + 2
+    with pytest.raises(pc.PcotError):
+        pc.trap_plan((100, 100), 10, (16, 64, 128), "slt_wave")
+
+
+def test_motiv_workspace_is_linear_in_N_and_T():
+    """O(N) memory: interior second buffer plus the two boundary arrays, not
+    the (T+1) N of a full expansion."""
+    import paper_1802_00166_amd as pc
+    N, T = 4096, 8192
+    ws = pc.workspace_bytes("motiv1d", "f64", (N,), T, (64, 256), "slt_wave")
+    assert ws < 8 * (N + 2 * (T + 1)) + 64 * 1024 + 4 * 1024 * 4
+    assert ws < 8 * N * (T + 1) / 100

@@ -1,13 +1,12 @@
 """The stored cost model on held-out problems: its tile choices against the
 exhaustive sweep and against one fixed tile for every shape (the method
-without the model), all timed here.  The top-3-verified choice must be within
-10% of the sweep (geometric mean); the unverified top-1 pick, whose
-prediction error (RMSE in ln time about 0.07 on the training sweeps and 0.2
-over all candidates of held-out problems) is comparable to the gap between
-the best candidates, within 20%; both must beat the fixed tile.
+without the model: the sweep best of the 4096^2 f64 problem), all timed here.
+The model's own top-1 pick must be within 10% of the sweep's best as a
+geometric mean, and beat the fixed tile.
 
-Held-out problems: instances of the uneven batch (their shapes come from the
-batch's own seeded stream, which the training sweeps never used).
+Held-out problems: 16 instances of the uneven batch (their shapes come from
+the batch's own seeded stream, which the training sweeps never used) and
+the 4096^2 f64 headline problem.
 """
 import math
 
@@ -17,7 +16,16 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-FIXED = ((16, 64, 128), "slt_wave")
+FIXED = ((16, 64, 256), "slt_wave")
+
+
+def _compare(tune, model, prob, schedules):
+    _, _, best_ms, recs = tune.sweep(prob, reps=5, warmup=1, schedules=schedules)
+    # the model's own pick (top 1 of the predictions), re-timed beside the sweep
+    _, _, pick_ms, _ = tune.tune(prob, tune.TUNE_MODEL_VERIFY, model, reps=5, warmup=1, topk=1,
+                                 schedules=schedules)
+    fixed_ms = {(tuple(r["tile"]), r["schedule"]): r["ms"] for r in recs}.get(FIXED)
+    return best_ms, pick_ms, fixed_ms
 
 
 def test_model_picks_within_ten_percent_of_sweep_and_beat_a_fixed_tile(gpu):
@@ -25,29 +33,23 @@ def test_model_picks_within_ten_percent_of_sweep_and_beat_a_fixed_tile(gpu):
     model = tune.load_default_model()
     if model is None:
         pytest.skip("no stored model (paper_1802_00166_amd/models/stencil.mlp)")
-    inst = synth.batched_instances(256)[3::43][:6]
-    ratios, gains, v3 = [], [], []
-    for ny, nx, T in inst:
-        prob = tune.problem("jacobi2d", "f32", (ny, nx), T)
-        _, _, best_ms, recs = tune.sweep(prob, reps=5, warmup=1, schedules=["slt_wave"])
-        # the model's own pick (top 1 of the predictions), re-timed beside the sweep
-        _, _, pick_ms, _ = tune.tune(prob, tune.TUNE_MODEL_VERIFY, model, reps=5, warmup=1, topk=1,
-                                     schedules=["slt_wave"])
-        # and the optional verification of the three best-predicted candidates
-        _, _, v3_ms, _ = tune.tune(prob, tune.TUNE_MODEL_VERIFY, model, reps=5, warmup=1, topk=3,
-                                   schedules=["slt_wave"])
-        v3.append(v3_ms / best_ms)
-        fixed_ms = {(tuple(r["tile"]), r["schedule"]): r["ms"] for r in recs}[FIXED]
+    probs = [("jacobi2d", "f32", (ny, nx), T) for ny, nx, T in synth.batched_instances(256)[3::16][:16]]
+    probs.append(("jacobi2d", "f64", (4096, 4096), 512))
+    ratios, gains = [], []
+    for kind, dtype, shape, T in probs:
+        prob = tune.problem(kind, dtype, shape, T)
+        best_ms, pick_ms, fixed_ms = _compare(tune, model, prob, ["slt_wave"])
         ratios.append(pick_ms / best_ms)
-        gains.append(fixed_ms / pick_ms)
-        print("%dx%d T=%d: sweep %.3f ms, model %.3f ms (x%.3f), fixed %.3f ms"
-              % (ny, nx, T, best_ms, pick_ms, pick_ms / best_ms, fixed_ms))
+        if fixed_ms is not None:
+            gains.append(fixed_ms / pick_ms)
+        print("%s %s T=%d: sweep %.3f ms, model %.3f ms (x%.3f), fixed %s ms"
+              % (dtype, "x".join(map(str, shape)), T, best_ms, pick_ms, pick_ms / best_ms,
+                 "%.3f" % fixed_ms if fixed_ms is not None else "n/a"))
     gm = math.exp(sum(math.log(r) for r in ratios) / len(ratios))
     gg = math.exp(sum(math.log(g) for g in gains) / len(gains))
-    g3 = math.exp(sum(math.log(r) for r in v3) / len(v3))
-    print("geomean model/sweep %.4f (top-3 verified %.4f), geomean gain over the fixed tile %.4f" % (gm, g3, gg))
-    assert g3 <= 1.10
-    assert gm <= 1.20
+    print("geomean model/sweep %.4f over %d problems (worst %.3f); geomean gain over the fixed tile %.4f"
+          % (gm, len(ratios), max(ratios), gg))
+    assert gm <= 1.10
     assert gg > 1.0
 
 
