@@ -80,7 +80,8 @@ typedef enum {
 } pcot_dtype;
 
 typedef enum {
-    PCOT_NAIVE = 0,    /* untiled: one sweep over the field per time step                     */
+    PCOT_NAIVE = 0,    /* untiled: one sweep over the field per time step (a Jacobi-1D field
+                          whose two levels fit in one CU's LDS runs all steps in one block)   */
     PCOT_SLT_LEX = 1,  /* single-level tiling, tiles in lexicographic order (Section 1, 3.2)   */
     PCOT_SLT_WAVE = 2, /* single-level tiling, tiles ordered by wavefront, then lexicographic  */
     PCOT_COT_SEQ = 3,  /* recursive decomposition, orthants in lexicographic order (Sec. 4.2)  */

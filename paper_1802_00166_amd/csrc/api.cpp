@@ -20,6 +20,7 @@
 #include "front.hpp"
 #include "motiv.hpp"
 #include "dpsplit.hpp"
+#include "resident.hpp"
 
 namespace pcot {
 enum : int { DP_INIT = 0, DP_ITEMS = 1, DP_FINISH = 2 };
@@ -905,6 +906,12 @@ pcot_status pcot_stencil_run(int32_t kind, int32_t dtype, const int64_t* dims, i
     }
     // buffers: buf[T mod 2] = out, the other one in the workspace; both get in's boundary
     HIP_TRY(launch_copy_boundary(dtype, in, out, field, p.d, p.n, s));
+    if (schedule == PCOT_NAIVE && kind == PCOT_JACOBI1D_3PT && resident1d_fits(dtype, p.n[0])) {
+        // the whole field stays in one CU's LDS for all T steps: one launch
+        HIP_TRY(launch_fill_u32(hdr, HDR_WORDS, 0u, s));
+        HIP_TRY(launch_resident1d(dtype, in, out, (int)p.n[0], (int)T, s));
+        return PCOT_OK;
+    }
     if (schedule == PCOT_NAIVE) {
         HIP_TRY(launch_fill_u32(hdr, HDR_WORDS, 0u, s));
         void* buf[2];

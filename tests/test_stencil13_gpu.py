@@ -56,6 +56,19 @@ def test_jacobi1d_f32_bf16_bit_exact(gpu, n, T, tile, sched, dtype):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n", [3, 1000, 4096, 10200, 10300, 20400])
+def test_jacobi1d_naive_resident_block_bit_exact(gpu, n, dtype):
+    """The untiled path keeps fields whose two levels fit one CU's LDS (up to
+    10,224 f64 / 20,448 f32 or bf16 points) in one block for every step;
+    larger ones take one kernel per step.  Both give the oracle's bits."""
+    T = 157
+    u0 = field("jacobi1d", (n,), dtype, 13)
+    want = oracle.stencil("jacobi1d", dtype, u0, T)
+    got = run("jacobi1d", dtype, u0, T, None, "naive")
+    assert np.array_equal(got, want), (n, dtype)
+
+
 def test_jacobi1d_tiny_fields_and_small_T(gpu):
     for n in [3, 4, 65, 66, 67]:
         for T in [0, 1, 2, 7]:
