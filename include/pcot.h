@@ -236,8 +236,12 @@ pcot_status pcot_error_norms_static(int32_t dtype, int32_t d, const int64_t* dim
  *          pcot_stream_status if not.
  *   C      device, N*N int64 row-major; C[(i-1)*N + (j-1)] receives the
  *          cost of A_i..A_j for i <= j.  The lower triangle is set to 0.
- *   tile   s[0] = s[1] = block size b of the (i, j) tiles (16..256, power of
- *          two), s[2] = k-block size (multiple of 16, <= b); t unused.
+ *   tile   s[0] = s[1] = block size b of the square (i, j) tiles, b in
+ *          {16, 32, 64} (the finishing pass holds three b x b tiles in LDS:
+ *          b = 128 would not fit); s[2] = k-chunk, a multiple of 16: the
+ *          off-diagonal splits of a tile pair are cut into work items of
+ *          this many splits; t unused.  Other sizes: PCOT_ERR_UNSUPPORTED /
+ *          PCOT_ERR_INVALID.
  *   schedule PCOT_SLT_WAVE (tile diagonals in order) or PCOT_COT_PAR
  *          (recursive halving of the padded (i, j) triangle; leaves grouped by
  *          the wavefronts of each split).

@@ -1,6 +1,7 @@
 // C ABI: argument validation, plan cache, workspace layout and launches.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -147,11 +148,21 @@ pcot_status validate(int32_t kind, int32_t dtype, const int64_t* dims, int64_t T
             if (tile->s[i] < 2) return fail(PCOT_ERR_INVALID, "tile.s[%d]=%d < 2 (dependence distance is 2)", i, tile->s[i]);
             p.b[i + 1] = tile->s[i];
         }
-        if (is_trap(schedule))
+        if (is_trap(schedule)) {
             for (int i = 0; i < 2; ++i)
                 if (tile->s[i] < 2 * tile->t + 2)
                     return fail(PCOT_ERR_INVALID, "trapezoid footprint s[%d]=%d < 2*t+2 = %d", i, tile->s[i],
                                 2 * tile->t + 2);
+            // the host plan lists every tile with its successors: bound its size
+            double tiles = (double)((T + tile->t - 1) / tile->t);
+            for (int i = 0; i < 2; ++i) {
+                const double period = 2.0 * tile->s[i] - 2.0 - 2.0 * tile->t;
+                tiles *= 2.0 * (std::ceil((double)dims[i] / period) + 1.0);
+            }
+            if (tiles > (double)(1 << 24))
+                return fail(PCOT_ERR_UNSUPPORTED, "trapezoid plan of about %.0f tiles (limit 2^24): use a larger tile",
+                            tiles);
+        }
         // The tiled executors address a field through one buffer resource
         // with 32-bit byte offsets and mask stores with the offset OOB
         // (0x7FFFFFF0).  Offsets they form reach one outermost slice (row,
@@ -528,7 +539,7 @@ pcot_status dp_validate(int64_t N, int64_t pmax, const pcot_tile* tile, int32_t 
         A.kc = tile->s[2] > 0 ? tile->s[2] : 256;
         if (tile->s[1] != tile->s[0]) return fail(PCOT_ERR_INVALID, "DP tiles are square: s[0] == s[1]");
     }
-    if (!dp_block_supported(A.b)) return fail(PCOT_ERR_UNSUPPORTED, "DP block size %d (supported: 32, 64)", A.b);
+    if (!dp_block_supported(A.b)) return fail(PCOT_ERR_UNSUPPORTED, "DP block size %d (supported: 16, 32, 64)", A.b);
     if (A.kc < 16 || A.kc % 16) return fail(PCOT_ERR_INVALID, "DP k-chunk %d: multiple of 16 required", A.kc);
     A.Np = (N + A.b - 1) / A.b * A.b;
     {

@@ -292,8 +292,12 @@ __global__ void __launch_bounds__(256) k_dp_ext(DPLaunch a) {
 // 1024 threads: a cell of the finishing pass gets 1024 / B lanes.
 template <typename V, int B, int R>
 __global__ void __launch_bounds__(1024) k_dp_fin(DPLaunch a) {
+    // a cell gets at most 32 lanes (the group minimum stays inside a half
+    // wave): with B = 16 the finishing pass uses the first 512 threads and
+    // the others only take part in the barriers
+    constexpr int FT = B * 32 < 1024 ? B * 32 : 1024;
     if ((int)blockIdx.x < a.ntiles)
-        dp_fin_tile<V, B, 1024>(a, blockIdx.x);
+        dp_fin_tile<V, B, FT>(a, blockIdx.x);
     else
         dp_ext_item<V, B, R, 1024>(a, blockIdx.x - a.ntiles);
 }
@@ -304,7 +308,7 @@ hipError_t launch_phase_t(const DPLaunch& a, int mode, hipStream_t s) {
         hipLaunchKernelGGL((k_dp_init<V>), dim3(2048), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    constexpr int R = B == 32 ? 2 : (B == 64 ? 4 : 8);
+    constexpr int R = B == 16 ? 1 : (B == 32 ? 2 : (B == 64 ? 4 : 8));
     if (mode == DP_ITEMS) {
         if (a.nitems > 0) hipLaunchKernelGGL((k_dp_ext<V, B, R>), dim3(a.nitems), dim3(256), 0, s, a);
     } else if (a.ntiles + a.nitems > 0) {
@@ -315,7 +319,7 @@ hipError_t launch_phase_t(const DPLaunch& a, int mode, hipStream_t s) {
 
 }  // namespace
 
-bool dp_block_supported(int b) { return b == 32 || b == 64; }
+bool dp_block_supported(int b) { return b == 16 || b == 32 || b == 64; }
 
 hipError_t launch_dp_pad(const long long* p, long long* pp, int Nout, int N, hipStream_t s) {
     hipLaunchKernelGGL(k_dp_pad, dim3((N + 256) / 256), dim3(256), 0, s, p, pp, Nout, N);
@@ -326,9 +330,11 @@ hipError_t launch_dp_pad(const long long* p, long long* pp, int Nout, int N, hip
 // of external items, or a finishing pass with the items that run beside it.
 hipError_t launch_dp_phase(bool wide, const DPLaunch& a, int mode, hipStream_t s) {
     if (!wide) {
+        if (a.b == 16) return launch_phase_t<unsigned, 16>(a, mode, s);
         if (a.b == 32) return launch_phase_t<unsigned, 32>(a, mode, s);
         return launch_phase_t<unsigned, 64>(a, mode, s);
     }
+    if (a.b == 16) return launch_phase_t<long long, 16>(a, mode, s);
     if (a.b == 32) return launch_phase_t<long long, 32>(a, mode, s);
     return launch_phase_t<long long, 64>(a, mode, s);
 }

@@ -10,18 +10,28 @@
 // Mapping: the block has by waves; thread (w, lane) owns column (jy0+w,
 // jx0+lane).  Levels are pipelined along jz: at step s, level l handles plane
 // jz0 + s - l, so the levels of one step are independent and one barrier per
-// step suffices.  Each level's output planes (with a two-wide halo in y and x
-// holding the neighbour tiles' values, prefetched one step ahead) sit in a
-// 4-slot LDS ring: plane jz being written, jz-1..jz-3 readable.  Ring 0 holds
-// the tile's input u_t0, streamed in plane by plane.  The planes below the
-// tile (z-face) come from the z-neighbour tile at tile start.  Stores: the
-// top level at every point, and the two-wide high faces in x, y and z of every
-// other level.  Points outside the interior are carried unchanged.
+// step suffices.  The input planes of every level but the first (outputs of
+// the level below, with a two-wide halo in y and x holding the neighbour
+// tiles' values) sit in a 4-slot LDS ring: plane jz being written, jz-1..jz-3
+// readable.  Ring 0 holds the tile's input u_t0, streamed in plane by plane.
+// The top level's outputs feed no level of the tile and go to memory only.
+// Ring-0 planes and halos come from tiles that finished before this one
+// started, so they are prefetched D steps ahead: a step is far shorter than
+// a round trip to HBM.  The planes below the tile (z-face) come from the
+// z-neighbour tile at tile start.  Stores: the top level at every point, and
+// the two-wide high faces in x, y and z of every other level.  Points outside
+// the interior are carried unchanged.
 #include "bufio.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
 #include <type_traits>
+
+// Steps between a prefetch and its use (1, 2 or 4: the step loop is unrolled
+// by four and a prefetch slot is the step it serves, mod the depth).
+#ifndef PCOT_H3D_PREFETCH
+#define PCOT_H3D_PREFETCH 2
+#endif
 
 namespace pcot {
 
@@ -43,7 +53,7 @@ template <> struct Ring<uint16_t> {
     static __device__ __forceinline__ float get(L v) { return bf16_to_f32(v); }
 };
 
-template <typename S, int BY, bool BND>
+template <typename S, int BY, int D, bool BND>
 __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, typename Ring<S>::L* lds) {
     using A = typename Tr<S>::A;
     using L = typename Ring<S>::L;
@@ -79,24 +89,32 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     auto ring = [&](int v, int jz, int ry, int rx) -> L& {
         return lds[((v * 4 + ((jz - jz0 + v + 3) & 3)) * RY + ry) * RX + rx];
     };
-    // ring v's value at skewed (jz, jy, jx): u_{t0+v} at the point
-    // (jz, jy, jx) - (t0+v-1), read from global; v must be wave-uniform
-    auto ldlvl = [&](int v, int jz, int jy, int jx) -> A {
-        const int t = t0 + v;  // buffer u_t
-        const int d = t - 1;
-        const int z = jz - d, y = jy - d, x = jx - d;
-        if (z < 0 || z >= nz || y < 0 || y >= ny) return A(0);
-        return IO<S>::ld(src_of(t), offs(z, y, x));
-    };
 
-    // ---- tile start: planes jz0-2, jz0-1 of every ring, and plane jz0 of ring 0
-    for (int v = 0; v <= nt; ++v) {
+    static_assert(D == 1 || D == 2 || D == 4, "prefetch depth divides the unroll");
+    // ---- tile start: planes jz0-2, jz0-1 of every ring, and plane jz0 of
+    // ring 0; all loads of a ring are issued before its LDS stores, so a ring
+    // costs one round trip to memory
+    constexpr int TS = (3 * PL + nthr - 1) / nthr;
+    for (int v = 0; v < nt; ++v) {
         const int np = v == 0 ? 3 : 2;
-        for (int e = threadIdx.x; e < np * PL; e += nthr) {
+        const int d = t0 + v - 1;  // ring v holds u_{t0+v} at (j - d)
+        const rsrc_t rs = src_of(t0 + v);
+        A tv[TS];
+#pragma unroll
+        for (int i = 0; i < TS; ++i) {
+            const int e = threadIdx.x + i * nthr;
             const int pz = e / PL, rem = e % PL;
-            const int ry = rem / RX, rx = rem % RX;
-            const int jz = jz0 - 2 + pz;
-            ring(v, jz, ry, rx) = RG::put(ldlvl(v, jz, jy0 - 2 + ry, jx0 - 2 + rx));
+            const int z = jz0 - 2 + pz - d, y = jy0 - 2 + rem / RX - d, x = jx0 - 2 + rem % RX - d;
+            const bool ok = e < np * PL && z >= 0 && z < nz && y >= 0 && y < ny;
+            tv[i] = IO<S>::ld(rs, ok ? offs(z, y, x) : OOB);
+        }
+#pragma unroll
+        for (int i = 0; i < TS; ++i) {
+            const int e = threadIdx.x + i * nthr;
+            if (e < np * PL) {
+                const int rem = e % PL;
+                ring(v, jz0 - 2 + e / PL, rem / RX, rem % RX) = RG::put(tv[i]);
+            }
         }
     }
     // Prefetch slots: every thread owns fixed positions of the ring-0 plane
@@ -105,10 +123,10 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     // unsigned compares per slot (32-bit multiplies are multi-pass on CDNA).
     const uint32_t PB = (uint32_t)ny * (uint32_t)nx * ES;  // bytes per plane
     constexpr int PF = (PL + nthr - 1) / nthr;             // ring-0 plane slots
-    A p0[PF];
+    A p0[D][PF];
     int p_lds[PF];        // in-plane LDS index, -1: idle
     uint32_t p_off[PF];   // byte offset at step 0 (mod 2^32)
-    bool p_yok[PF];       // row inside the array
+    bool p_yok[PF];       // slot in use and row inside the array
     const int d0 = t0 - 1;  // ring 0 holds u_t0 at (j - d0)
     // pf0_load(jz0 + s + 2) reads plane z = jz0 + s + 2 - d0: live while 0 <= z < nz
     const int zc0 = jz0 + 2 - d0;
@@ -118,28 +136,37 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
         const int pr = e / RX, pc = e % RX;
         const int y = jy0 - 2 + pr - d0, x = jx0 - 2 + pc - d0;
         p_lds[i] = e < PL ? e : -1;
-        p_yok[i] = y >= 0 && y < ny;
+        p_yok[i] = e < PL && y >= 0 && y < ny;
         p_off[i] = (uint32_t)zc0 * PB + (uint32_t)(y * nx + x) * (uint32_t)ES;
     }
+    // Every prefetch load is issued, with an out-of-range offset where
+    // nothing is wanted, so that each step issues the same memory
+    // instructions without branches and the compiler's waits count exactly
+    // (a load skipped on some path makes it wait for every access in flight).
     const rsrc_t r0 = src_of(t0);
-    auto pf0_load = [&](int s) {  // ring-0 plane jz0 + s + 2
-        const bool zok = (uint32_t)(zc0 + s) < (uint32_t)nz;  // wave-uniform
+    auto pf0_load = [&](A (&dst)[PF], int s, bool live) {  // ring-0 plane jz0 + s + 2
+        // the wave-uniform plane condition as an opaque VGPR mask OR-ed into
+        // the offsets (a select on it is turned into a branch)
+        uint32_t zm = (live && (uint32_t)(zc0 + s) < (uint32_t)nz) ? 0u : (uint32_t)OOB;
+        asm volatile("" : "+v"(zm));
 #pragma unroll
         for (int i = 0; i < PF; ++i)
-            if (p_lds[i] >= 0)
-                p0[i] = IO<S>::ld(r0, (zok && p_yok[i]) ? (int)(p_off[i] + (uint32_t)s * PB) : OOB);
+            dst[i] = IO<S>::ld(r0, (int)((p_yok[i] ? p_off[i] + (uint32_t)s * PB : (uint32_t)OOB) | zm));
     };
-    auto pf0_store = [&](int jz) {
+    auto pf0_store = [&](const A (&src)[PF], int jz) {
         L* pl = &ring(0, jz, 0, 0);
 #pragma unroll
         for (int i = 0; i < PF; ++i)
-            if (p_lds[i] >= 0) pl[p_lds[i]] = RG::put(p0[i]);
+            if (p_lds[i] >= 0) pl[p_lds[i]] = RG::put(src[i]);
     };
-    // halo of plane jz of ring v (v >= 1): rows ry = 0, 1 (all RX columns) and
-    // columns rx = 0, 1 of rows 2..RY-1: 2*RX + 2*by values per level
+    // halo of plane jz of ring v (1 <= v < nt): rows ry = 0, 1 (all RX
+    // columns) and columns rx = 0, 1 of rows 2..RY-1: 2*RX + 2*by values per
+    // level whose outputs are read in the tile (all but the top one)
     constexpr int HL = 2 * RX + 2 * by;
     constexpr int HPF = BY == 16 ? 2 : (BY == 8 ? 4 : 8);  // halo slots per thread per step (all levels)
-    A hv[HPF];
+    // both parity candidates of every halo value stay in registers until the
+    // slot is published: selecting right after the loads would wait for them
+    A hvE[D][HPF], hvO[D][HPF];
     // level (nt: idle), in-plane LDS index, first step with z >= 0 (far
     // below any step when the row lies outside the array), offset at step 0
     int h_l[HPF], h_lds[HPF], h_zlo[HPF];
@@ -164,45 +191,65 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     // differ with the parity of t; a buffer descriptor must be wave-uniform,
     // so both are read (the other offset out of range) and the lane keeps its own.
     const rsrc_t rhE = src_of(t0 + 1), rhO = src_of(t0 + 2);  // rings v = l+1, l even / odd
-    auto halo_load = [&](int s) {  // halos of the planes the levels write at step s
+    auto halo_load = [&](A (&dE)[HPF], A (&dO)[HPF], int s) {  // halos of the planes the levels write at step s
 #pragma unroll
         for (int i = 0; i < HPF; ++i) {
             const int l = h_l[i];
-            if (l < nt && (uint32_t)(s - l) < (uint32_t)bz) {
-                const bool ok = (uint32_t)(s - h_zlo[i]) < (uint32_t)nz;
-                const int o = ok ? (int)(h_off[i] + (uint32_t)s * PB) : OOB;
-                const bool ev = (l & 1) == 0;
-                const A a = IO<S>::ld(rhE, ev ? o : OOB), b = IO<S>::ld(rhO, ev ? OOB : o);
-                hv[i] = ev ? a : b;
-            }
+            const bool ok = l + 1 < nt && (uint32_t)(s - l) < (uint32_t)bz && (uint32_t)(s - h_zlo[i]) < (uint32_t)nz;
+            const int o = ok ? (int)(h_off[i] + (uint32_t)s * PB) : OOB;
+            const bool ev = (l & 1) == 0;
+            dE[i] = IO<S>::ld(rhE, ev ? o : OOB);
+            dO[i] = IO<S>::ld(rhO, ev ? OOB : o);
         }
     };
-    auto halo_store = [&](int s) {
+    auto halo_store = [&](const A (&sE)[HPF], const A (&sO)[HPF], int s) {
 #pragma unroll
         for (int i = 0; i < HPF; ++i) {
             const int l = h_l[i], sl = s - l;
-            if (l < nt && (uint32_t)sl < (uint32_t)bz) (&ring(l + 1, jz0 + sl, 0, 0))[h_lds[i]] = RG::put(hv[i]);
+            if (l + 1 < nt && (uint32_t)sl < (uint32_t)bz)
+                (&ring(l + 1, jz0 + sl, 0, 0))[h_lds[i]] = RG::put((l & 1) ? sO[i] : sE[i]);
         }
     };
-    pf0_load(-1);  // plane jz0 + 1
-    halo_load(0);
+    // the data published at step q: ring-0 plane jz0 + q + 1 (level 0 reads
+    // planes up to jz0 + bz - 1) and the halos of the planes written at step
+    // q; slot q mod D
+    auto fetch = [&](auto dc, int q) {
+        constexpr int d = decltype(dc)::value;
+        pf0_load(p0[d], q - 1, q <= bz - 2);
+        halo_load(hvE[d], hvO[d], q);
+    };
+    // ring 0's slot is written at every step (past the tile's last plane
+    // with values nobody reads): the plane it held was last read the step
+    // before, and a load whose value were dropped on some path would again
+    // cost a full wait
+    auto publish = [&](auto dc, int q) {
+        constexpr int d = decltype(dc)::value;
+        pf0_store(p0[d], jz0 + q + 1);
+        halo_store(hvE[d], hvO[d], q);
+    };
+    // steps padded to the unroll (the extra steps have no live level), so no
+    // step is skipped by a branch
+    const int nsteps = (bz + nt - 1 + 3) & ~3;
+    fetch(std::integral_constant<int, 0>{}, 0);
+    if constexpr (D > 1) fetch(std::integral_constant<int, 1>{}, 1);
+    if constexpr (D > 2) {
+        fetch(std::integral_constant<int, 2>{}, 2);
+        fetch(std::integral_constant<int, 3>{}, 3);
+    }
     __syncthreads();
 
     const int jy = jy0 + w, jx = jx0 + lane;
     const int ry = w + 2, rx = lane + 2;
     const int tc = (ry - 1) * RX + (rx - 1);  // the thread's centre input within a plane
-    const int nsteps = bz + nt - 1;
     auto step = [&](auto qc, int s) {
         // slots of this step (s % 4 = Q): written, z+ plane, centre plane, z- plane
         constexpr int Q = decltype(qc)::value;
         constexpr int SW = Q, SP = (Q + 3) & 3, SC = (Q + 2) & 3, SM = (Q + 1) & 3;
         // publish the prefetched ring-0 plane jz0+s+1 and the halos of this
-        // step's output planes, then start the next prefetches
-        pf0_store(jz0 + s + 1);
-        halo_store(s);
+        // step's output planes, then refill the slot for step s + D
+        publish(std::integral_constant<int, Q % D>{}, s);
         __syncthreads();
-        pf0_load(s);
-        halo_load(s + 1);
+        fetch(std::integral_constant<int, Q % D>{}, s + D);
         for (int l = 0; l < nt; ++l) {
             const int jz = jz0 + s - l;
             if (jz < jz0 || jz >= jz0 + bz) continue;  // uniform
@@ -215,7 +262,7 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
             const int z = jz - t, y = jy - t, x = jx - t;
             const bool in = !BND || inside(z, y, x);
             const A out = in ? v : u;
-            lds[(l + 1) * (4 * PL) + SW * PL + ry * RX + rx] = RG::put(out);
+            if (l + 1 < nt) lds[(l + 1) * (4 * PL) + SW * PL + ry * RX + rx] = RG::put(out);
             const bool face = t == ttop || lane >= BX - 2 || w >= by - 2 || jz >= jz0 + bz - 2;
             // level l writes u_{t0+l+1}: the buffers of rings l+1 (hoisted descriptors)
             if (face && in) IO<S>::st((l & 1) ? rhO : rhE, offs(z, y, x), out);
@@ -224,9 +271,9 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     };
     for (int s0 = 0; s0 < nsteps; s0 += 4) {
         step(std::integral_constant<int, 0>{}, s0);
-        if (s0 + 1 < nsteps) step(std::integral_constant<int, 1>{}, s0 + 1);
-        if (s0 + 2 < nsteps) step(std::integral_constant<int, 2>{}, s0 + 2);
-        if (s0 + 3 < nsteps) step(std::integral_constant<int, 3>{}, s0 + 3);
+        step(std::integral_constant<int, 1>{}, s0 + 1);
+        step(std::integral_constant<int, 2>{}, s0 + 2);
+        step(std::integral_constant<int, 3>{}, s0 + 3);
     }
 }
 
@@ -238,9 +285,9 @@ __global__ void __launch_bounds__(64 * BY) k_tiled3d(TiledLaunch Lc) {
     run_queued_tile<3, true>(Lc, &s_tk, &s_go, [&](const TiledProblem& P, const int* k) {
         // tiles whose every point lies inside the array skip the per-point test
         if (tile_interior<3>(P, k))
-            exec3d<S, BY, false>(P, k, reinterpret_cast<L*>(smem_raw));
+            exec3d<S, BY, PCOT_H3D_PREFETCH, false>(P, k, reinterpret_cast<L*>(smem_raw));
         else
-            exec3d<S, BY, true>(P, k, reinterpret_cast<L*>(smem_raw));
+            exec3d<S, BY, PCOT_H3D_PREFETCH, true>(P, k, reinterpret_cast<L*>(smem_raw));
     });
 }
 
@@ -258,7 +305,7 @@ template <typename S>
 hipError_t launch_dtype(const int* b, const TiledLaunch& Lc, hipStream_t s) {
     if (Lc.nq <= 0) return hipSuccess;
     const int bt = b[0], by = b[2];
-    const size_t lds = (size_t)(bt + 1) * 4 * (by + 2) * 66 * sizeof(typename Ring<S>::L);
+    const size_t lds = (size_t)bt * 4 * (by + 2) * 66 * sizeof(typename Ring<S>::L);
     switch (by) {
         case 2: return launch_by<S, 2>(Lc, lds, s);
         case 4: return launch_by<S, 4>(Lc, lds, s);
@@ -275,10 +322,11 @@ bool tiled3d_supported(const int* b, int lds_elem) {
     if (b[3] != 64) return false;
     if (b[2] != 2 && b[2] != 4 && b[2] != 8 && b[2] != 16) return false;
     if (b[1] < 2 || b[0] < 1 || b[0] > 16) return false;
-    // halo prefetch slots: HPF * threads >= bt * (2*66 + 2*by)
+    // halo prefetch slots: HPF * threads >= (bt - 1) * (2*66 + 2*by)
     const int hpf = b[2] == 16 ? 2 : (b[2] == 8 ? 4 : 8);
-    if (hpf * 64 * b[2] < b[0] * (2 * 66 + 2 * b[2])) return false;
-    const size_t lds = (size_t)(b[0] + 1) * 4 * (b[2] + 2) * 66 * lds_elem;
+    if (hpf * 64 * b[2] < (b[0] - 1) * (2 * 66 + 2 * b[2])) return false;
+    // rings: the tile's input and the outputs of every level but the top one
+    const size_t lds = (size_t)b[0] * 4 * (b[2] + 2) * 66 * lds_elem;
     return lds <= 150 * 1024;
 }
 

@@ -140,3 +140,12 @@ def test_chain_split_reconstructs_cost(gpu):
     import sys
     sys.setrecursionlimit(10000)
     assert cost(0, N - 1) == int(C[0, N - 1])
+
+
+@pytest.mark.parametrize("sched", ["slt_wave", "cot_par"])
+@pytest.mark.parametrize("N,pmax,kc", [(300, 100, 16), (517, 100, 48), (200, 1000, 32)])
+def test_chain_block16_bit_exact(gpu, N, pmax, kc, sched):
+    """16 x 16 tiles (32- and 64-bit paths)."""
+    p = synth.randint(synth.test_rng(300 + N), N + 1, 1, pmax)
+    want = _upper(oracle.matrix_chain(p))
+    assert np.array_equal(_upper(_run(p, pmax, (0, 16, 16, kc), sched)), want)

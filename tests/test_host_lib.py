@@ -202,3 +202,14 @@ def test_motiv_workspace_is_linear_in_N_and_T():
     ws = pc.workspace_bytes("motiv1d", "f64", (N,), T, (64, 256), "slt_wave")
     assert ws < 8 * (N + 2 * (T + 1)) + 64 * 1024 + 4 * 1024 * 4
     assert ws < 8 * N * (T + 1) / 100
+
+
+def test_trap_plan_size_bound():
+    """A concurrent-start plan is listed tile by tile on the host: plans of
+    more than 2^24 tiles are refused before any is built."""
+    import paper_1802_00166_amd as pc
+    with pytest.raises(pc.PcotError) as e:
+        pc.trap_plan((4096, 4096), 1 << 20, (8, 64, 128))
+    assert "2^24" in str(e.value)
+    with pytest.raises(pc.PcotError):   # the workspace query returns 0 for it
+        pc.workspace_bytes("jacobi2d", "f64", (4096, 4096), 1 << 20, (8, 64, 128), "trap")
