@@ -44,6 +44,7 @@ namespace pcot {
 namespace {
 
 constexpr int NT = 512;  // threads per block
+constexpr int NB_GS = 8, NB_FDTD = 4;  // copy-in loads per thread and field in flight together
 constexpr double FDTD_CE = 0.25, FDTD_CH = 0.5;
 
 struct Geo {
@@ -88,10 +89,20 @@ __device__ void exec_gs(const TiledProblem& P, const int* k, double* lds) {
     const uint32_t bytes = (uint32_t)ny * (uint32_t)nx * 8;
     const rsrc_t rf = make_rsrc(uptr(P.buf0), bytes);
     const int cells = g.Hy * g.Hx;
-    for (int q = threadIdx.x; q < cells; q += NT) {
-        const int y = g.oy + q / g.Hx, x = g.ox + q % g.Hx;
-        const bool in = y >= 0 && y < ny && x >= 0 && x < nx;
-        lds[q] = IO<double>::ld(rf, in ? (y * nx + x) * 8 : OOB);
+    // copy-in: a batch of loads in flight per thread before its LDS stores
+    // (a load followed at once by its store would cost a round trip each)
+    for (int q0 = threadIdx.x; q0 < cells; q0 += NT * NB_GS) {
+        double v[NB_GS];
+#pragma unroll
+        for (int b = 0; b < NB_GS; ++b) {
+            const int q = q0 + b * NT;
+            const int y = g.oy + q / g.Hx, x = g.ox + q % g.Hx;
+            const bool in = q < cells && y >= 0 && y < ny && x >= 0 && x < nx;
+            v[b] = IO<double>::ld(rf, in ? (y * nx + x) * 8 : OOB);
+        }
+#pragma unroll
+        for (int b = 0; b < NB_GS; ++b)
+            if (q0 + b * NT < cells) lds[q0 + b * NT] = v[b];
     }
     __syncthreads();
     const int npair = g.nt * g.by;
@@ -124,12 +135,26 @@ __device__ void exec_fdtd(const TiledProblem& P, const int* k, double* lds) {
     double* ex = lds;
     double* ey = lds + cells;
     double* hz = lds + 2 * cells;
-    for (int q = threadIdx.x; q < cells; q += NT) {
-        const int i = g.oy + q / g.Hx, j = g.ox + q % g.Hx;
-        const int o = (i >= 0 && i < ny && j >= 0 && j < nx) ? (i * nx + j) * 8 : OOB;
-        ex[q] = IO<double>::ld(rex, o);
-        ey[q] = IO<double>::ld(rey, o);
-        hz[q] = IO<double>::ld(rhz, o);
+    for (int q0 = threadIdx.x; q0 < cells; q0 += NT * NB_FDTD) {
+        double vx[NB_FDTD], vy[NB_FDTD], vh[NB_FDTD];
+#pragma unroll
+        for (int b = 0; b < NB_FDTD; ++b) {
+            const int q = q0 + b * NT;
+            const int i = g.oy + q / g.Hx, j = g.ox + q % g.Hx;
+            const int o = (q < cells && i >= 0 && i < ny && j >= 0 && j < nx) ? (i * nx + j) * 8 : OOB;
+            vx[b] = IO<double>::ld(rex, o);
+            vy[b] = IO<double>::ld(rey, o);
+            vh[b] = IO<double>::ld(rhz, o);
+        }
+#pragma unroll
+        for (int b = 0; b < NB_FDTD; ++b) {
+            const int q = q0 + b * NT;
+            if (q < cells) {
+                ex[q] = vx[b];
+                ey[q] = vy[b];
+                hz[q] = vh[b];
+            }
+        }
     }
     __syncthreads();
     const int npair = g.nt * g.by;
