@@ -190,12 +190,26 @@ __device__ __forceinline__ V group_min(V v) {
 }
 
 // -------------------------------------------------------- finishing part ---
-// One block per tile.  Cells are taken by anti-diagonals of (u, v) =
-// ((I+1)B-1-i, j-JB): a cell's internal operands lie below it (same column)
-// or left of it (same row), i.e. on earlier anti-diagonals.  Each cell is
-// handled by TPC threads that split its internal k range, then min-reduce.
-template <typename V, int B, int NT>
+// One block (WAVE: one wave) per tile.  Cells are taken by anti-diagonals of
+// (u, v) = ((I+1)B-1-i, j-JB): a cell's internal operands lie below it (same
+// column) or left of it (same row), i.e. on earlier anti-diagonals.  Each cell
+// is handled by TPC threads that split its internal k range, then
+// min-reduce.  With one wave the anti-diagonals need no block barrier: the
+// LDS accesses of a wave are carried out in the order it issues them, so a
+// wave barrier (which only keeps the compiler from moving them) orders the
+// steps.
+template <typename V, int B, int NT, bool WAVE = false>
 __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
+    static_assert(!WAVE || NT == 64, "one wave");
+    auto sync = [] {
+        if constexpr (WAVE) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    };
     constexpr int TPC = NT / B;  // threads per cell
     __shared__ V T[B][B + 1];     // tile (I, J)
     __shared__ V DI[B][B + 1];    // tile (I, I) (unused when I == J)
@@ -218,7 +232,7 @@ __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
     }
     if (tid <= B) PA[tid] = (V)a.p[I * B + tid];
     if (tid < B) PB[tid] = (V)a.p[J * B + tid + 1];
-    __syncthreads();
+    sync();
     // The row operand C[i][k] of a split k in block I lies in tile (I, I) (the
     // tile itself when diagonal); its column operand C[k+1][j] in the tile.
     // For k in block J the row operand is in the tile and the column operand
@@ -265,7 +279,7 @@ __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
             const V mm = T[li][lj];  // external minimum (INF on diagonal tiles)
             T[li][lj] = best < mm ? best : mm;
         }
-        __syncthreads();
+        sync();
     }
     for (int e = tid; e < B * B; e += NT) {
         const int r = e / B, c = e % B;
@@ -289,17 +303,28 @@ __global__ void __launch_bounds__(256) k_dp_ext(DPLaunch a) {
 // [0, ntiles) finish tiles, the rest take items.  The two sets touch
 // disjoint tiles (items only read finished tiles and atomically lower cells
 // of next-phase tiles).
-// 1024 threads: a cell of the finishing pass gets 1024 / B lanes.
+// 1024 threads: a cell of the finishing pass gets 1024 / B lanes (b = 32, 64).
 template <typename V, int B, int R>
 __global__ void __launch_bounds__(1024) k_dp_fin(DPLaunch a) {
-    // a cell gets at most 32 lanes (the group minimum stays inside a half
-    // wave): with B = 16 the finishing pass uses the first 512 threads and
-    // the others only take part in the barriers
+    // a cell gets at most 32 lanes (the group minimum stays inside a half wave)
     constexpr int FT = B * 32 < 1024 ? B * 32 : 1024;
     if ((int)blockIdx.x < a.ntiles)
         dp_fin_tile<V, B, FT>(a, blockIdx.x);
     else
         dp_ext_item<V, B, R, 1024>(a, blockIdx.x - a.ntiles);
+}
+
+// b = 16: the finishing pass of a tile is one wave (4 lanes per cell), in
+// 256-thread blocks shared with the external items (at N = 4096 1.56x the
+// 1024-thread pass; at b = 32 two lanes per cell walk 32 splits each and the
+// block pass stays 3.4x faster).
+template <typename V, int B, int R>
+__global__ void __launch_bounds__(256) k_dp_finw(DPLaunch a) {
+    if ((int)blockIdx.x < a.ntiles) {
+        if (threadIdx.x < 64) dp_fin_tile<V, B, 64, true>(a, blockIdx.x);
+    } else {
+        dp_ext_item<V, B, R, 256>(a, blockIdx.x - a.ntiles);
+    }
 }
 
 template <typename V, int B>
@@ -312,7 +337,10 @@ hipError_t launch_phase_t(const DPLaunch& a, int mode, hipStream_t s) {
     if (mode == DP_ITEMS) {
         if (a.nitems > 0) hipLaunchKernelGGL((k_dp_ext<V, B, R>), dim3(a.nitems), dim3(256), 0, s, a);
     } else if (a.ntiles + a.nitems > 0) {
-        hipLaunchKernelGGL((k_dp_fin<V, B, R>), dim3(a.ntiles + a.nitems), dim3(1024), 0, s, a);
+        if constexpr (B == 16)
+            hipLaunchKernelGGL((k_dp_finw<V, B, R>), dim3(a.ntiles + a.nitems), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_dp_fin<V, B, R>), dim3(a.ntiles + a.nitems), dim3(1024), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -83,13 +83,14 @@ std::vector<std::pair<pcot_tile, int32_t>> candidates(const pcot_problem* p, uin
                     for (int bx : {64, 128, 256}) tiles.push_back(mk(bt, by, bx, 0));
             break;
         case PCOT_HEAT3D_7PT:
-            for (int bt : {2, 4, 8})
+            for (int bt : {2, 3, 4, 8})
                 for (int bz : {16, 64, 256})
                     for (int by : {2, 4, 8, 16}) tiles.push_back(mk(bt, bz, by, 64));
             break;
         case PCOT_MATRIX_CHAIN:
-            for (int b : {32, 64})
-                for (int kc : {32, 64, 128, 256}) tiles.push_back(mk(0, b, b, kc));
+            for (int b : {16, 32, 64})
+                for (int kc : {16, 32, 64, 128, 256})
+                    if (kc >= b || b == 16) tiles.push_back(mk(0, b, b, kc));
             break;
         default: return out;
     }

@@ -72,6 +72,16 @@ def sample_large(n, seed):
     return out
 
 
+def sample_heat3d(n, seed):
+    """Heat-3D training shapes, extents in [64, 400] (the 512^3 benchmark
+    problem and its neighbourhood stay out), T in [16, 128], the three
+    storage types in turn."""
+    rng = np.random.default_rng(seed)
+    dts = ["f64", "f32", "bf16"]
+    return [("heat3d", dts[i % 3], tuple(int(v) for v in rng.integers(64, 401, size=3)), int(rng.integers(16, 129)))
+            for i in range(n)]
+
+
 def batch_instances(count=256, seed_stream=4):
     """Shapes of the uneven batch, from the shared seeded generator when the
     repository's input module is present, else from numpy (documented)."""
@@ -151,6 +161,7 @@ def main():
     ap.add_argument("--seed", type=int, default=77)
     ap.add_argument("--large-shapes", type=int, default=8,
                     help="extra training shapes with extents in [2048, 4096] (T in [128, 512])")
+    ap.add_argument("--heat3d-shapes", type=int, default=9, help="Heat-3D training sweeps")
     ap.add_argument("--extra-records", default=None,
                     help="JSON-lines records of earlier training sweeps to train on as well")
     ap.add_argument("--skip-small", action="store_true",
@@ -176,6 +187,7 @@ def main():
     if not args.skip_small:
         train += [("jacobi1d", "f64", (n,), T) for n, T in [(1024, 256), (4096, 1000), (16384, 512), (65536, 256)]]
     train += sample_large(args.large_shapes, args.seed + 1)
+    train += sample_heat3d(args.heat3d_shapes, args.seed + 2)
     records = []
     if args.extra_records:
         with open(args.extra_records) as f:
@@ -209,6 +221,10 @@ def main():
     log("trained on %d records in %.2f s: final loss %.4f, train RMSE(ln ms) %.3f" %
         (len(records), train_s, model.final_loss, rmse))
     return evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_start)
+
+
+# Heat-3D problems held out of the training sweeps
+HELD_OUT_HEAT3D = [("heat3d", "f32", (256, 192, 320), 48), ("heat3d", "f64", (300, 300, 300), 60)]
 
 
 def evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_start):
@@ -259,6 +275,8 @@ def evaluate_all(args, tune, model, records, train, sweep_s, train_s, rmse, t_st
     step = max(1, len(inst) // max(1, args.eval_batch))
     for (ny, nx, T) in inst[::step][:args.eval_batch]:
         evaluate("jacobi2d", "f32", (ny, nx), T, two, fixed if fixed[1] in two else (fixed[0], "cot_par"))
+    for kind, dtype, shape, T in HELD_OUT_HEAT3D:
+        evaluate(kind, dtype, shape, T, two, None)
 
     ratios = [e["pick_over_best"] for e in evals]
     gains = [e["gain_over_fixed"] for e in evals if e["gain_over_fixed"]]

@@ -238,6 +238,24 @@ BATCH_UNIFORM_TILES = [(16, 64, 128), (32, 64, 128), (16, 64, 256), (32, 64, 256
                        (32, 32, 256), (16, 128, 256), (64, 64, 128)]
 
 
+def batch_model_uniform(model: Model, kind: str, dtype: str, shapes, Ts, schedule: str = "slt_wave"):
+    """One tile for every instance of a batch, chosen by the cost model: the
+    candidate (runnable for every instance) with the smallest predicted sum
+    of the instances' times.  The instances of a batch run together, so the
+    batch's time follows their summed work, not one instance's critical path
+    (a per-instance pick follows the latter and favours small tiles)."""
+    probs = [problem(kind, dtype, sh, TT) for sh, TT in zip(shapes, Ts)]
+    common = None
+    for prob in probs:
+        tiles = {tuple(c[0]) for c in candidates(prob, [schedule])}
+        common = tiles if common is None else common & tiles
+    cand = sorted(common)
+    recs = [{"feat": list(features(prob, t, schedule)), "tile": list(t), "schedule": schedule}
+            for t in cand for prob in probs]
+    ms = np.asarray(model.predict_ms(recs), dtype=np.float64).reshape(len(cand), len(probs))
+    return cand[int(np.argmin(ms.sum(axis=1)))]
+
+
 def batch_model_tiles(model: Model, kind: str, dtype: str, shapes, Ts, schedule: str = "slt_wave"):
     """Per-instance tiles of a batch from the cost model.  The batch runs one
     executor instance, so b_x is common: per instance the best predicted

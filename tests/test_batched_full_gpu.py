@@ -1,7 +1,8 @@
 """The 256-instance uneven batch exactly as the benchmark launches it: every
 instance of the one persistent launch equals the oracle bit for bit, with the
-best uniform tile and with the cost model's per-instance tiles, run eagerly
-and replayed from a HIP graph (with other work between replays)."""
+best uniform tile, the cost model's tile for the batch and its per-instance
+tiles, run eagerly and replayed from a HIP graph (with other work between
+replays)."""
 import numpy as np
 import pytest
 
@@ -35,10 +36,12 @@ def _tiles(name, shapes, Ts):
     model = tune.load_default_model()
     if model is None:
         pytest.skip("no trained cost model")
+    if name == "model_batch":  # the benchmark's value: the model's one tile for the batch
+        return [tune.batch_model_uniform(model, "jacobi2d", "f32", shapes, Ts)] * len(shapes)
     return tune.batch_model_tiles(model, "jacobi2d", "f32", shapes, Ts)
 
 
-@pytest.mark.parametrize("which", ["uniform", "model"])
+@pytest.mark.parametrize("which", ["uniform", "model_batch", "model"])
 def test_batched_256_benchmark_launch_bit_exact(gpu, which):
     import torch
     import paper_1802_00166_amd as pc

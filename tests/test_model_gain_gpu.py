@@ -5,8 +5,9 @@ The model's own top-1 pick must be within 10% of the sweep's best as a
 geometric mean, and beat the fixed tile.
 
 Held-out problems: 16 instances of the uneven batch (their shapes come from
-the batch's own seeded stream, which the training sweeps never used) and
-the 4096^2 f64 headline problem.
+the batch's own seeded stream, which the training sweeps never used), the
+4096^2 f64 headline problem and a Heat-3D problem (256 x 192 x 320, T = 48,
+f32).
 """
 import math
 
@@ -35,6 +36,8 @@ def test_model_picks_within_ten_percent_of_sweep_and_beat_a_fixed_tile(gpu):
         pytest.skip("no stored model (paper_1802_00166_amd/models/stencil.mlp)")
     probs = [("jacobi2d", "f32", (ny, nx), T) for ny, nx, T in synth.batched_instances(256)[3::16][:16]]
     probs.append(("jacobi2d", "f64", (4096, 4096), 512))
+    # a Heat-3D problem held out of the training sweeps
+    probs.append(("heat3d", "f32", (256, 192, 320), 48))
     ratios, gains = [], []
     for kind, dtype, shape, T in probs:
         prob = tune.problem(kind, dtype, shape, T)

@@ -19,7 +19,7 @@ def test_sweep_best_is_the_fastest_record(gpu):
 def test_dp_and_3d_sweeps(gpu):
     from paper_1802_00166_amd import tune
     tile, sched, ms, recs = tune.sweep(tune.problem("matrix_chain", "", (700,), 100), reps=2, warmup=1)
-    assert len(recs) == 16 and ms == min(r["ms"] for r in recs) and tile[1] in (32, 64)
+    assert len(recs) == 24 and ms == min(r["ms"] for r in recs) and tile[1] in (16, 32, 64)
     tile, sched, ms, recs = tune.sweep(tune.problem("heat3d", "f32", (40, 50, 70), 10), reps=2, warmup=1,
                                        schedules=["slt_wave"])
     assert len(recs) >= 10 and ms == min(r["ms"] for r in recs)
