@@ -552,10 +552,11 @@ def _batch_bytes(tiles, inst):
 def workload_batched(args, pc, torch):
     """The uneven batch: 256 f32 instances in one persistent launch, replayed
     from a HIP graph.  The value is the cost model's batch choice: one tile
-    for every instance, the candidate with the smallest predicted summed
-    time.  Beside it, for context: a sweep over uniform tiles and the model's
-    per-instance picks (one b_x for the batch), which follow each instance's
-    stand-alone critical path rather than the batch's throughput."""
+    for every instance, the model's best for one problem that fills the
+    device as the batch does (tune.batch_model_uniform).  Beside it, for
+    context: a sweep over uniform tiles and the model's per-instance picks
+    (one b_x for the batch), which follow each instance's stand-alone
+    critical path rather than the batch's throughput."""
     import numpy as np
     import synth
     from paper_1802_00166_amd import tune

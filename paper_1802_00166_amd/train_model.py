@@ -157,7 +157,7 @@ def main():
     ap.add_argument("--shapes", type=int, default=64)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--eval-batch", type=int, default=16, help="held-out uneven-batch instances evaluated")
-    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=1500)
     ap.add_argument("--seed", type=int, default=77)
     ap.add_argument("--large-shapes", type=int, default=8,
                     help="extra training shapes with extents in [2048, 4096] (T in [128, 512])")

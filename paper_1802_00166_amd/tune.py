@@ -239,21 +239,27 @@ BATCH_UNIFORM_TILES = [(16, 64, 128), (32, 64, 128), (16, 64, 256), (32, 64, 256
 
 
 def batch_model_uniform(model: Model, kind: str, dtype: str, shapes, Ts, schedule: str = "slt_wave"):
-    """One tile for every instance of a batch, chosen by the cost model: the
-    candidate (runnable for every instance) with the smallest predicted sum
-    of the instances' times.  The instances of a batch run together, so the
-    batch's time follows their summed work, not one instance's critical path
-    (a per-instance pick follows the latter and favours small tiles)."""
-    probs = [problem(kind, dtype, sh, TT) for sh, TT in zip(shapes, Ts)]
-    common = None
-    for prob in probs:
-        tiles = {tuple(c[0]) for c in candidates(prob, [schedule])}
-        common = tiles if common is None else common & tiles
+    """One tile for every instance of a batch, chosen by the cost model.  The
+    instances of a batch run together and fill the device, so what a tile
+    costs there is its throughput on a full device, not an instance's
+    stand-alone time (bound by its critical path, which favours small
+    tiles).  The model is asked for its best tile on one problem that fills
+    the device as the batch does: the batch's total extent as a cube of its
+    dimension (each side capped at 4096, the largest trained extent), at the
+    extent-weighted mean T; among the candidates runnable for every
+    instance."""
+    d = len(shapes[0])
+    vols = [float(np.prod(sh)) for sh in shapes]
+    side = int(min(4096, round(sum(vols) ** (1.0 / d))))
+    tw = max(1, int(round(sum(v * TT for v, TT in zip(vols, Ts)) / sum(vols))))
+    rep = problem(kind, dtype, (side,) * d, tw)
+    common = {tuple(c[0]) for c in candidates(rep, [schedule])}
+    for sh, TT in zip(shapes, Ts):
+        common &= {tuple(c[0]) for c in candidates(problem(kind, dtype, sh, TT), [schedule])}
     cand = sorted(common)
-    recs = [{"feat": list(features(prob, t, schedule)), "tile": list(t), "schedule": schedule}
-            for t in cand for prob in probs]
-    ms = np.asarray(model.predict_ms(recs), dtype=np.float64).reshape(len(cand), len(probs))
-    return cand[int(np.argmin(ms.sum(axis=1)))]
+    ms = model.predict_ms([{"feat": list(features(rep, t, schedule)), "tile": list(t), "schedule": schedule}
+                          for t in cand])
+    return cand[int(np.argmin(ms))]
 
 
 def batch_model_tiles(model: Model, kind: str, dtype: str, shapes, Ts, schedule: str = "slt_wave"):
