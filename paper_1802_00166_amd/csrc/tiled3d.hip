@@ -17,7 +17,12 @@
 // The top level's outputs feed no level of the tile and go to memory only.
 // Ring-0 planes and halos come from tiles that finished before this one
 // started, so they are prefetched D steps ahead: a step is far shorter than
-// a round trip to HBM.  The planes below the tile (z-face) come from the
+// a round trip to HBM.  For the common b_t the level count of a full tile is
+// a compile-time constant: every step then runs every level (inactive ones,
+// in the pipeline's fill and drain, skip their LDS write and store through
+// an out-of-range offset), so each step issues the same memory instructions
+// and the compiler's waits for a prefetch count exactly instead of covering
+// every store in flight.  The planes below the tile (z-face) come from the
 // z-neighbour tile at tile start.  Stores: the top level at every point, and
 // the two-wide high faces in x, y and z of every other level.  Points outside
 // the interior are carried unchanged.
@@ -53,7 +58,7 @@ template <> struct Ring<uint16_t> {
     static __device__ __forceinline__ float get(L v) { return bf16_to_f32(v); }
 };
 
-template <typename S, int BY, int D, bool BND>
+template <typename S, int BY, int D, bool BND, int NTC>
 __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, typename Ring<S>::L* lds) {
     using A = typename Tr<S>::A;
     using L = typename Ring<S>::L;
@@ -68,7 +73,7 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     constexpr int by = BY;
     constexpr int RY = by + 2, PL = RY * RX;  // plane of the ring, with halo
     const int t0 = k[0] * bt;
-    const int nt = min(bt, P.T - t0);
+    const int nt = NTC > 0 ? NTC : min(bt, P.T - t0);
     const int ttop = t0 + nt - 1;
     const int jz0 = 1 + k[1] * bz, jy0 = 1 + k[2] * by, jx0 = 1 + k[3] * BX;
     const uint32_t bytes = (uint32_t)nz * (uint32_t)ny * (uint32_t)nx * ES;
@@ -227,11 +232,12 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
         pf0_store(p0[d], jz0 + q + 1);
         halo_store(hvE[d], hvO[d], q);
     };
-    // The level loop's trip count is known only at run time, so the compiler
-    // cannot count the face stores it issues and a wait for a prefetch also
-    // waits for every store issued since.  f64: the step's prefetch goes after
-    // its stores, so such a wait covers only accesses at least a step old
-    // (+8%; for f32 and bf16 it measured 5% slower or no different).
+    // On the generic path the level loop's trip count is known only at run
+    // time, so the compiler cannot count the face stores it issues and a wait
+    // for a prefetch also waits for every store issued since.  f64: the step's
+    // prefetch goes after its stores, so such a wait covers only accesses at
+    // least a step old (+8% on the generic path; for f32 and bf16 it measured
+    // 5% slower or no different).
     constexpr bool FETCH_AFTER = sizeof(S) == 8;
     // steps padded to the unroll (the extra steps have no live level), so no
     // step is skipped by a branch
@@ -256,6 +262,26 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
         publish(std::integral_constant<int, Q % D>{}, s);
         __syncthreads();
         if constexpr (!FETCH_AFTER) fetch(std::integral_constant<int, Q % D>{}, s + D);
+        if constexpr (NTC > 0) {
+            // every level of a full tile, active or not
+#pragma unroll
+            for (int l = 0; l < NTC; ++l) {
+                const int jz = jz0 + s - l;
+                const bool act = jz >= jz0 && jz < jz0 + bz;  // uniform
+                const int t = t0 + l;
+                const L* rl = lds + l * (4 * PL) + tc;
+                const A u = RG::get(rl[SC * PL]);
+                const A v = Tr<S>::rnd(heat3(u, RG::get(rl[SC * PL + 1]), RG::get(rl[SC * PL - 1]),
+                                             RG::get(rl[SC * PL + RX]), RG::get(rl[SC * PL - RX]),
+                                             RG::get(rl[SP * PL]), RG::get(rl[SM * PL])));
+                const int z = jz - t, y = jy - t, x = jx - t;
+                const bool in = !BND || inside(z, y, x);
+                const A out = in ? v : u;
+                if (l + 1 < NTC && act) lds[(l + 1) * (4 * PL) + SW * PL + ry * RX + rx] = RG::put(out);
+                const bool face = t == ttop || lane >= BX - 2 || w >= by - 2 || jz >= jz0 + bz - 2;
+                IO<S>::st((l & 1) ? rhO : rhE, (act && face && in) ? offs(z, y, x) : OOB, out);
+            }
+        } else
         for (int l = 0; l < nt; ++l) {
             const int jz = jz0 + s - l;
             if (jz < jz0 || jz >= jz0 + bz) continue;  // uniform
@@ -284,28 +310,50 @@ __device__ __forceinline__ void exec3d(const TiledProblem& P, const int* k, type
     }
 }
 
-template <typename S, int BY>
+template <typename S, int BY, int BT>
 __global__ void __launch_bounds__(64 * BY) k_tiled3d(TiledLaunch Lc) {
     extern __shared__ char smem_raw[];
     using L = typename Ring<S>::L;
     __shared__ int s_tk, s_go;
     run_queued_tile<3, true>(Lc, &s_tk, &s_go, [&](const TiledProblem& P, const int* k) {
         // tiles whose every point lies inside the array skip the per-point test
-        if (tile_interior<3>(P, k))
-            exec3d<S, BY, PCOT_H3D_PREFETCH, false>(P, k, reinterpret_cast<L*>(smem_raw));
-        else
-            exec3d<S, BY, PCOT_H3D_PREFETCH, true>(P, k, reinterpret_cast<L*>(smem_raw));
+        const bool full = BT > 0 && P.b[0] == BT && (k[0] + 1) * BT <= P.T;
+        if (full) {
+            if (tile_interior<3>(P, k))
+                exec3d<S, BY, PCOT_H3D_PREFETCH, false, BT>(P, k, reinterpret_cast<L*>(smem_raw));
+            else
+                exec3d<S, BY, PCOT_H3D_PREFETCH, true, BT>(P, k, reinterpret_cast<L*>(smem_raw));
+        } else if (tile_interior<3>(P, k)) {
+            exec3d<S, BY, PCOT_H3D_PREFETCH, false, 0>(P, k, reinterpret_cast<L*>(smem_raw));
+        } else {
+            exec3d<S, BY, PCOT_H3D_PREFETCH, true, 0>(P, k, reinterpret_cast<L*>(smem_raw));
+        }
     });
 }
 
-template <typename S, int BY>
-hipError_t launch_by(const TiledLaunch& Lc, size_t lds, hipStream_t s) {
+template <typename S, int BY, int BT>
+hipError_t launch_bt(const TiledLaunch& Lc, size_t lds, hipStream_t s) {
     if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_tiled3d<S, BY>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const hipError_t e = hipFuncSetAttribute((const void*)k_tiled3d<S, BY, BT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_tiled3d<S, BY>), dim3(Lc.nq), dim3(64 * BY), lds, s, Lc);
+    hipLaunchKernelGGL((k_tiled3d<S, BY, BT>), dim3(Lc.nq), dim3(64 * BY), lds, s, Lc);
     return hipGetLastError();
+}
+
+// b_t with a kernel of its own (its full tiles take the fixed-level path);
+// other b_t run every tile on the generic path
+template <typename S, int BY>
+hipError_t launch_by(const TiledLaunch& Lc, int bt, size_t lds, hipStream_t s) {
+    switch (bt) {
+        case 2: return launch_bt<S, BY, 2>(Lc, lds, s);
+        case 3: return launch_bt<S, BY, 3>(Lc, lds, s);
+        case 4: return launch_bt<S, BY, 4>(Lc, lds, s);
+        case 6: return launch_bt<S, BY, 6>(Lc, lds, s);
+        case 8: return launch_bt<S, BY, 8>(Lc, lds, s);
+        case 12: return launch_bt<S, BY, 12>(Lc, lds, s);
+        default: return launch_bt<S, BY, 0>(Lc, lds, s);
+    }
 }
 
 template <typename S>
@@ -314,10 +362,10 @@ hipError_t launch_dtype(const int* b, const TiledLaunch& Lc, hipStream_t s) {
     const int bt = b[0], by = b[2];
     const size_t lds = (size_t)bt * 4 * (by + 2) * 66 * sizeof(typename Ring<S>::L);
     switch (by) {
-        case 2: return launch_by<S, 2>(Lc, lds, s);
-        case 4: return launch_by<S, 4>(Lc, lds, s);
-        case 8: return launch_by<S, 8>(Lc, lds, s);
-        case 16: return launch_by<S, 16>(Lc, lds, s);
+        case 2: return launch_by<S, 2>(Lc, bt, lds, s);
+        case 4: return launch_by<S, 4>(Lc, bt, lds, s);
+        case 8: return launch_by<S, 8>(Lc, bt, lds, s);
+        case 16: return launch_by<S, 16>(Lc, bt, lds, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -83,7 +83,7 @@ std::vector<std::pair<pcot_tile, int32_t>> candidates(const pcot_problem* p, uin
                     for (int bx : {64, 128, 256}) tiles.push_back(mk(bt, by, bx, 0));
             break;
         case PCOT_HEAT3D_7PT:
-            for (int bt : {2, 3, 4, 8})
+            for (int bt : {2, 3, 4, 6, 8, 12})
                 for (int bz : {16, 64, 256})
                     for (int by : {2, 4, 8, 16}) tiles.push_back(mk(bt, bz, by, 64));
             break;

@@ -21,7 +21,7 @@ def test_candidate_grids_are_the_runnable_subset():
          [(bt, by, bx) for bt in (4, 8, 16, 32, 64) for by in (16, 32, 64, 128, 256) for bx in (64, 128, 256)]),
         ("jacobi1d", "f64", (4096,), 1000, [(bt, bx) for bt in (16, 32, 64, 128, 256) for bx in (64, 128, 256)]),
         ("heat3d", "f32", (512, 512, 512), 128,
-         [(bt, bz, by, 64) for bt in (2, 3, 4, 8) for bz in (16, 64, 256) for by in (2, 4, 8, 16)]),
+         [(bt, bz, by, 64) for bt in (2, 3, 4, 6, 8, 12) for bz in (16, 64, 256) for by in (2, 4, 8, 16)]),
     ]:
         prob = tune.problem(kind, dtype, shape, T)
         got = tune.candidates(prob)
