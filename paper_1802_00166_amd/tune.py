@@ -123,7 +123,9 @@ class Model:
         self.ptr = ctypes.c_void_p(ptr)
 
     def __del__(self):
-        if getattr(self, "ptr", None) is not None and self.ptr.value:
+        # at interpreter exit the binding may already be torn down: then the
+        # process frees everything anyway
+        if getattr(self, "ptr", None) is not None and self.ptr.value and callable(pcot_model_free):
             pcot_model_free(self.ptr)
             self.ptr = None
 
@@ -238,16 +240,16 @@ BATCH_UNIFORM_TILES = [(16, 64, 128), (32, 64, 128), (16, 64, 256), (32, 64, 256
                        (32, 32, 256), (16, 128, 256), (64, 64, 128)]
 
 
-def batch_model_uniform(model: Model, kind: str, dtype: str, shapes, Ts, schedule: str = "slt_wave"):
-    """One tile for every instance of a batch, chosen by the cost model.  The
-    instances of a batch run together and fill the device, so what a tile
-    costs there is its throughput on a full device, not an instance's
-    stand-alone time (bound by its critical path, which favours small
-    tiles).  The model is asked for its best tile on one problem that fills
-    the device as the batch does: the batch's total extent as a cube of its
+def batch_model_uniform(model: Model, kind: str, dtype: str, shapes, Ts, schedule: str = "slt_wave", topk: int = 1):
+    """Tiles for a whole batch (one tile for every instance), ranked by the
+    cost model; the `topk` best, best first.  The instances of a batch run
+    together and fill the device, so what a tile costs there is its
+    throughput on a full device, not an instance's stand-alone time (bound by
+    its critical path, which favours small tiles).  The model ranks the
+    candidates runnable for every instance on one problem that fills the
+    device as the batch does: the batch's total extent as a cube of its
     dimension (each side capped at 4096, the largest trained extent), at the
-    extent-weighted mean T; among the candidates runnable for every
-    instance."""
+    extent-weighted mean T."""
     d = len(shapes[0])
     vols = [float(np.prod(sh)) for sh in shapes]
     side = int(min(4096, round(sum(vols) ** (1.0 / d))))
@@ -259,7 +261,8 @@ def batch_model_uniform(model: Model, kind: str, dtype: str, shapes, Ts, schedul
     cand = sorted(common)
     ms = model.predict_ms([{"feat": list(features(rep, t, schedule)), "tile": list(t), "schedule": schedule}
                           for t in cand])
-    return cand[int(np.argmin(ms))]
+    order = np.argsort(np.asarray(ms), kind="stable")
+    return [cand[int(i)] for i in order[:max(1, topk)]]
 
 
 def batch_model_tiles(model: Model, kind: str, dtype: str, shapes, Ts, schedule: str = "slt_wave"):

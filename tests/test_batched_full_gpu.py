@@ -37,7 +37,7 @@ def _tiles(name, shapes, Ts):
     if model is None:
         pytest.skip("no trained cost model")
     if name == "model_batch":  # the benchmark's value: the model's one tile for the batch
-        return [tune.batch_model_uniform(model, "jacobi2d", "f32", shapes, Ts)] * len(shapes)
+        return [tune.batch_model_uniform(model, "jacobi2d", "f32", shapes, Ts)[0]] * len(shapes)
     return tune.batch_model_tiles(model, "jacobi2d", "f32", shapes, Ts)
 
 
