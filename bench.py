@@ -43,7 +43,7 @@ MOTIV_TILE = (64, 256)
 TRAP_CANDIDATES = [((16, 64, 128), "trap"), ((8, 64, 128), "trap"), ((8, 64, 128), "diamond"),
                    ((8, 32, 128), "trap")]
 # Heat-3D 512^3, T = 128: the tile each storage type is benchmarked with
-HEAT3D_TILES = {"f64": (3, 64, 16, 64), "f32": (4, 64, 8, 64), "bf16": (8, 64, 8, 64)}
+HEAT3D_TILES = {"f64": (3, 64, 16, 64), "f32": (4, 64, 8, 64), "bf16": (4, 64, 8, 64)}
 
 HBM_PEAK_GBS = 8000.0
 # FP64 vector: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 non-fused FP64 ops/s
