@@ -252,6 +252,11 @@ __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
             lj = v;          // j = J*B + lj
             live = diag ? li < lj : true;
             if (live) {
+                // every lane of the cell starts from the cell's external
+                // minimum (INF on diagonal tiles), read with the operands so
+                // that the step has one round of LDS reads; only this cell
+                // writes it, at the end of this step
+                best = T[li][lj];
                 const V w = PA[li] * PB[lj];  // p[i] * p[j+1]
                 // block I: local k in [li, kA1); block J: local k in [0, lj)
                 const int kA1 = diag ? lj : B - 1;
@@ -275,10 +280,7 @@ __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
         }
         // min over the cell's TPC threads (adjacent lanes of one wave)
         best = group_min<TPC>(best);
-        if (act && part == 0 && live) {
-            const V mm = T[li][lj];  // external minimum (INF on diagonal tiles)
-            T[li][lj] = best < mm ? best : mm;
-        }
+        if (act && part == 0 && live) T[li][lj] = best;
         sync();
     }
     for (int e = tid; e < B * B; e += NT) {
