@@ -161,16 +161,19 @@ __device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
 
 // Minimum over groups of TPC adjacent lanes (TPC in {2, ..., 32}) with DPP
 // lane moves: swap neighbours, swap pairs within a quad, mirror the two quads
-// of each half row (lane i of the 8 meets lane 7-i), mirror the row of 16,
-// then exchange the two rows of 32 (swizzle, lane ^ 16), so every lane ends
-// with the group's minimum.
+// of each half row (lane i of the 8 meets lane 7-i), mirror the row of 16;
+// every lane of a row then holds the row's minimum.  A group of 32 (two rows)
+// ends with a broadcast of lane 15 of each even row into the odd row after
+// it, so the group's last lane (in the odd row) holds the minimum.  Only the
+// group's last lane's result is defined.
 __device__ __forceinline__ unsigned dpp_move(unsigned v, int ctrl) {
     switch (ctrl) {
         case 0: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
         case 1: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
         case 2: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
         case 3: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
-        default: return (unsigned)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);  // lane ^ 16 within 32 lanes
+        // row_bcast:15 into rows 1 and 3; rows 0 and 2 keep their own value
+        default: return (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false);
     }
 }
 __device__ __forceinline__ long long dpp_move(long long v, int ctrl) {
@@ -210,34 +213,41 @@ __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
             __syncthreads();
         }
     };
-    constexpr int TPC = NT / B;  // threads per cell
-    __shared__ V T[B][B + 1];     // tile (I, J)
-    __shared__ V DI[B][B + 1];    // tile (I, I) (unused when I == J)
-    __shared__ V DJ[B][B + 1];    // tile (J, J) (unused when I == J)
-    __shared__ V PA[B + 1];  // p[I*B .. I*B + B]: p[i] of the tile's rows, p[k+1] for k in block I
-    __shared__ V PB[B];      // p[J*B + 1 .. J*B + B]: p[j+1] of its columns, p[k+1] for k in block J
+    constexpr int TPC = NT / B;    // threads per cell
+    constexpr int WS = 2 * B + 1;  // row stride of W
+    constexpr int SS = B + 1;      // row stride of S
+    // A cell's in-tile splits, indexed x: x in [li, kA1) are the splits k of
+    // block I (local k = x), x in [B, B + lj) those of block J (local k =
+    // x - B).  Both parts read their operands from one array each:
+    //   W[r][x]  row operand C[i][k]:    x < B tile (I, I) (the tile itself
+    //            when diagonal), x >= B the tile (I, J);
+    //   S[y][c]  column operand C[k+1][j], y = x + 1: y < B the tile (I, J),
+    //            y > B tile (J, J);
+    //   PC[y]    p[k+1]: y <= B p[I*B + y], y > B p[J*B + y - B].
+    // The tile is held twice (in W's right half, or left half when diagonal,
+    // and in S's upper half) and every cell is written to both.
+    __shared__ V W[B * WS];
+    __shared__ V S[2 * B * SS];
+    __shared__ V PC[2 * B + 1];
     const int2 tj = a.tiles[tile];
     const int I = tj.x, J = tj.y;
     const int N = a.N;
     V* Cw = (V*)a.Cw;
     const int tid = threadIdx.x;
     const bool diag = I == J;
+    const int wt = diag ? 0 : B;  // the tile's column offset in W
     for (int e = tid; e < B * B; e += NT) {
         const int r = e / B, c = e % B;
-        T[r][c] = Cw[(size_t)(I * B + r) * N + J * B + c];
+        const V t = Cw[(size_t)(I * B + r) * N + J * B + c];
+        W[r * WS + wt + c] = t;
+        S[r * SS + c] = t;
         if (!diag) {
-            DI[r][c] = Cw[(size_t)(I * B + r) * N + I * B + c];
-            DJ[r][c] = Cw[(size_t)(J * B + r) * N + J * B + c];
+            W[r * WS + c] = Cw[(size_t)(I * B + r) * N + I * B + c];
+            S[(B + r) * SS + c] = Cw[(size_t)(J * B + r) * N + J * B + c];
         }
     }
-    if (tid <= B) PA[tid] = (V)a.p[I * B + tid];
-    if (tid < B) PB[tid] = (V)a.p[J * B + tid + 1];
+    for (int y = tid; y <= 2 * B; y += NT) PC[y] = (V)a.p[y <= B ? I * B + y : J * B + y - B];
     sync();
-    // The row operand C[i][k] of a split k in block I lies in tile (I, I) (the
-    // tile itself when diagonal); its column operand C[k+1][j] in the tile.
-    // For k in block J the row operand is in the tile and the column operand
-    // in tile (J, J).
-    const V(*RA)[B + 1] = diag ? T : DI;
     const int cell = tid / TPC, part = tid % TPC;
     for (int s = 0; s <= 2 * B - 2; ++s) {
         // cell index along the anti-diagonal: u from max(0, s-B+1)
@@ -256,11 +266,11 @@ __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
                 // minimum (INF on diagonal tiles), read with the operands so
                 // that the step has one round of LDS reads; only this cell
                 // writes it, at the end of this step
-                best = T[li][lj];
-                const V w = PA[li] * PB[lj];  // p[i] * p[j+1]
-                // block I: local k in [li, kA1); block J: local k in [0, lj)
-                const int kA1 = diag ? lj : B - 1;
-                const int n1 = kA1 - li, n = n1 + (diag ? 0 : lj);
+                best = S[li * SS + lj];
+                const V w = PC[li] * PC[B + 1 + lj];  // p[i] * p[j+1]
+                const int n1 = (diag ? lj : B - 1) - li, n = n1 + (diag ? 0 : lj);
+                const int shiftA = li, shiftB = B - n1;
+                const V* Wr = W + li * WS;
                 // a fixed, unrolled number of slots per thread (at most 2B - 2
                 // splits per cell), so that all LDS reads of a step are in
                 // flight together; a slot past n reads a valid cell and is
@@ -268,26 +278,26 @@ __device__ __forceinline__ void dp_fin_tile(const DPLaunch& a, int tile) {
 #pragma unroll
                 for (int it = 0; it < (2 * B + TPC - 1) / TPC; ++it) {
                     const int q = part + it * TPC;
-                    const bool inA = q < n1;
-                    const int ka = min(li + q, B - 2), kb = max(min(q - n1, B - 2), 0);
-                    const V* rop = inA ? &RA[li][ka] : &T[li][kb];
-                    const V* cop = inA ? &T[ka + 1][lj] : &DJ[kb + 1][lj];
-                    const V pk = inA ? PA[ka + 1] : PB[kb];
-                    const V cand = DV<V>::add(DV<V>::madw(w, pk, *rop), *cop);
+                    const int x = min(q + (q < n1 ? shiftA : shiftB), 2 * B - 2);
+                    const V cand = DV<V>::add(DV<V>::madw(w, PC[x + 1], Wr[x]), S[(x + 1) * SS + lj]);
                     best = (q < n && cand < best) ? cand : best;
                 }
             }
         }
-        // min over the cell's TPC threads (adjacent lanes of one wave)
+        // min over the cell's TPC threads (adjacent lanes of one wave), held
+        // by the group's last lane
         best = group_min<TPC>(best);
-        if (act && part == 0 && live) T[li][lj] = best;
+        if (act && part == TPC - 1 && live) {
+            S[li * SS + lj] = best;
+            W[li * WS + wt + lj] = best;
+        }
         sync();
     }
     for (int e = tid; e < B * B; e += NT) {
         const int r = e / B, c = e % B;
         const int gi = I * B + r, gj = J * B + c;
         if (gi <= gj) {
-            const V v = T[r][c];
+            const V v = S[r * SS + c];
             Cw[(size_t)gi * N + gj] = v;
             if (gj < a.Nout) a.C[(size_t)gi * a.Nout + gj] = (long long)v;
         }
