@@ -93,24 +93,29 @@ __global__ void k_dp_init(DPLaunch a) {
 // ------------------------------------------------------- external part ---
 // One block per work item: a B x B output tile, k in [k0, k1).  Each thread
 // owns an R x R micro-tile; operand tiles go through LDS in KT-deep slices
-// (A transposed so a thread's R rows are contiguous).
-// NT threads per block; the first 256 own the micro-tiles, the rest (when
-// NT > 256, in the launch shared with a finishing pass) only help stage.
+// (A transposed so a thread's R rows are contiguous).  Every load of a slice
+// is issued before its LDS stores, so a slice costs one memory round trip,
+// and a slice takes a whole k-chunk of up to 64 splits (16 for B = 64, where
+// the finishing pass that shares the kernel leaves less LDS); the A panel is
+// read along its rows (consecutive k), the B panel along its rows
+// (consecutive j).
+// NT threads per block, each owning one micro-tile ((B/R)^2 == NT).
 template <typename V, int B, int R, int NT>
 __device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
-    constexpr int KT = 16;
-    constexpr int TPR = B / R;  // threads per row of micro-tiles (TPR*TPR == 256)
-    static_assert(TPR * TPR == 256, "micro-tile layout");
-    __shared__ V As[KT][B];     // As[kk][r] = C[I*B + r][k0 + kk]
-    __shared__ V Bs[KT][B];     // Bs[kk][c] = C[k0 + kk + 1][J*B + c]
-    __shared__ V Ps[KT];        // p[k + 1]
+    constexpr int KT = B <= 32 ? 64 : 16;
+    constexpr int PER = KT * B / NT;  // values per thread and panel in a slice
+    constexpr int TPR = B / R;        // threads per row of micro-tiles
+    static_assert(TPR * TPR == NT, "micro-tile layout");
+    static_assert(PER >= 1 && PER * NT == KT * B && NT >= KT, "staging layout");
+    __shared__ V As[KT][B + 1];  // As[kk][r] = C[I*B + r][k0 + kk]
+    __shared__ V Bs[KT][B];      // Bs[kk][c] = C[k0 + kk + 1][J*B + c]
+    __shared__ V Ps[KT];         // p[k + 1]
     const int4 it = a.items[item];
     const int I = it.x >> 16, J = it.x & 0xFFFF;  // target tile (I, J)
     const int N = a.N;
     const V* Cw = (const V*)a.Cw;
     const int tid = threadIdx.x;
-    const bool on = tid < 256;
-    const int tr = (tid & 255) / TPR, tc = tid % TPR;  // micro-tile coordinates
+    const int tr = tid / TPR, tc = tid % TPR;  // micro-tile coordinates
     const int row0 = I * B + tr * R, col0 = J * B + tc * R;
     V w[R][R], m[R][R];
 #pragma unroll
@@ -121,42 +126,52 @@ __device__ __forceinline__ void dp_ext_item(const DPLaunch& a, int item) {
             m[r][c] = DV<V>::INF;
         }
     for (int k0 = it.y; k0 < it.z; k0 += KT) {
-        // stage KT columns of the row panel and KT rows of the column panel
-        for (int e = tid; e < KT * B; e += NT) {
-            const int kk = e / B, x = e % B;
-            const int k = k0 + kk;
-            const bool ok = k < it.z;
-            // past the end of the range: a candidate of INF, which never wins
-            As[kk][x] = ok ? Cw[(size_t)(I * B + x) * N + k] : DV<V>::INF;
-            Bs[kk][x] = ok ? Cw[(size_t)(k + 1) * N + J * B + x] : (V)0;
+        // past the end of the range: a candidate of INF, which never wins
+        V ra[PER], rb[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + u * NT;
+            const int ka = e % KT, xa = e / KT, kb = e / B, xb = e % B;
+            ra[u] = k0 + ka < it.z ? Cw[(size_t)(I * B + xa) * N + k0 + ka] : DV<V>::INF;
+            rb[u] = k0 + kb < it.z ? Cw[(size_t)(k0 + kb + 1) * N + J * B + xb] : (V)0;
         }
-        if (tid < KT) Ps[tid] = (k0 + tid < it.z) ? (V)a.p[k0 + tid + 1] : (V)0;
+        const V rp = (tid < KT && k0 + tid < it.z) ? (V)a.p[k0 + tid + 1] : (V)0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + u * NT;
+            As[e % KT][e / KT] = ra[u];
+            Bs[e / B][e % B] = rb[u];
+        }
+        if (tid < KT) Ps[tid] = rp;
         __syncthreads();
+        // the slice's rows in use, rounded up to the unroll (rows past the
+        // range hold INF / 0); the same for the whole block
+        const int kn = (min(KT, it.z - k0) + 3) & ~3;
+        {
+#pragma unroll 4
+            for (int kk = 0; kk < kn; ++kk) {
+                V av[R], bv[R];
 #pragma unroll
-        for (int kk = 0; kk < (on ? KT : 0); ++kk) {
-            V av[R], bv[R];
+                for (int r = 0; r < R; ++r) av[r] = As[kk][tr * R + r];
 #pragma unroll
-            for (int r = 0; r < R; ++r) av[r] = As[kk][tr * R + r];
+                for (int c = 0; c < R; ++c) bv[c] = Bs[kk][tc * R + c];
+                const V pk = Ps[kk];
 #pragma unroll
-            for (int c = 0; c < R; ++c) bv[c] = Bs[kk][tc * R + c];
-            const V pk = Ps[kk];
+                for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int c = 0; c < R; ++c) {
-                    const V q = DV<V>::madw(w[r][c], pk, av[r]) + bv[c];
-                    m[r][c] = q < m[r][c] ? q : m[r][c];
-                }
+                    for (int c = 0; c < R; ++c) {
+                        const V qv = DV<V>::madw(w[r][c], pk, av[r]) + bv[c];
+                        m[r][c] = qv < m[r][c] ? qv : m[r][c];
+                    }
+            }
         }
         __syncthreads();
     }
     V* Cm = (V*)a.Cw;
-    if (on) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int c = 0; c < R; ++c) DV<V>::amin(Cm + (size_t)(row0 + r) * N + col0 + c, m[r][c]);
-    }
+        for (int c = 0; c < R; ++c) DV<V>::amin(Cm + (size_t)(row0 + r) * N + col0 + c, m[r][c]);
 }
 
 // Minimum over groups of TPC adjacent lanes (TPC in {2, ..., 32}) with DPP
@@ -323,7 +338,7 @@ __global__ void __launch_bounds__(1024) k_dp_fin(DPLaunch a) {
     if ((int)blockIdx.x < a.ntiles)
         dp_fin_tile<V, B, FT>(a, blockIdx.x);
     else
-        dp_ext_item<V, B, R, 1024>(a, blockIdx.x - a.ntiles);
+        dp_ext_item<V, B, B / 32, 1024>(a, blockIdx.x - a.ntiles);
 }
 
 // b = 16: the finishing pass of a tile is one wave (4 lanes per cell), in
